@@ -1,0 +1,131 @@
+"""Seeded synthetic workloads (numpy only; no integrator arithmetic here).
+
+Each generator returns a dict of float64 arrays in the structure-of-arrays
+layouts of the C ABI ([d][n] states, [p] or [p][n] parameters, [K] or [K][n]
+output nodes) plus the solver settings.  The same arrays feed the HIP path and
+the CPU oracle.
+
+The shapes follow the paper's three ensembles (Sections "Stellar streams",
+"Dark energy", "Spin precession"); the exact draws are this project's synthetic
+stand-ins for the paper's (unpublished) ensembles and data.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def _rng(seed):
+    return np.random.Generator(np.random.PCG64(seed))
+
+
+def loghalo_ics(rng, n, v0, q, rc):
+    """Orbits in the flattened logarithmic halo (eq:loghalo).
+
+    Position (R cos phi, R sin phi, z) with R ~ U[0.5, 2], z ~ U[-0.3, 0.3],
+    phi ~ U[0, 2 pi).  Speed = local circular speed v0 R / sqrt(R^2 + z^2/q^2
+    + rc^2) times N(1, 0.1); direction tilted from the azimuthal unit vector by
+    alpha ~ U[0, 0.3] rad towards cos(beta) R_hat + sin(beta) z_hat,
+    beta ~ U[0, 2 pi).  v0, q, rc may be scalars or [n] arrays.
+    """
+    R = rng.uniform(0.5, 2.0, n)
+    z = rng.uniform(-0.3, 0.3, n)
+    ph = rng.uniform(0.0, 2.0 * np.pi, n)
+    vcirc = v0 * R / np.sqrt(R * R + z * z / (q * q) + rc * rc)
+    speed = vcirc * rng.normal(1.0, 0.1, n)
+    alpha = rng.uniform(0.0, 0.3, n)
+    beta = rng.uniform(0.0, 2.0 * np.pi, n)
+    Rhat = np.stack([np.cos(ph), np.sin(ph), np.zeros(n)])
+    phat = np.stack([-np.sin(ph), np.cos(ph), np.zeros(n)])
+    zhat = np.stack([np.zeros(n), np.zeros(n), np.ones(n)])
+    dirv = np.cos(alpha) * phat + np.sin(alpha) * (np.cos(beta) * Rhat + np.sin(beta) * zhat)
+    y0 = np.empty((6, n))
+    y0[0] = R * np.cos(ph)
+    y0[1] = R * np.sin(ph)
+    y0[2] = z
+    y0[3:] = speed * dirv
+    return y0
+
+
+def orbits_forward(n=1000, seed=1):
+    """1,000 orbits, shared (v0, q, rc) = (1, 0.9, 0.1), t in [0, 50],
+    Dopri5 at rtol 1e-8 / atol 1e-10, 64 output times 50 k / 64."""
+    rng = _rng(seed)
+    theta = np.array([1.0, 0.9, 0.1])
+    y0 = loghalo_ics(rng, n, *theta)
+    return dict(rhs="loghalo", tableau="dopri5", y0=y0, theta=theta, t0=0.0, t1=50.0,
+                rtol=1e-8, atol=1e-10, t_out=50.0 * np.arange(1, 65) / 64.0)
+
+
+def orbits_uneven(n=100_000, seed=2):
+    """Uneven batch: per-orbit v0 ~ U[0.9, 1.1], q ~ U[0.7, 1], rc ~ U[0.05, 0.3],
+    t_end ~ logU[10, 500], rtol ~ logU[1e-9, 1e-6] (atol = rtol), Tsit5,
+    final state only."""
+    rng = _rng(seed)
+    v0 = rng.uniform(0.9, 1.1, n)
+    q = rng.uniform(0.7, 1.0, n)
+    rc = rng.uniform(0.05, 0.3, n)
+    y0 = loghalo_ics(rng, n, v0, q, rc)
+    t1 = np.exp(rng.uniform(np.log(10.0), np.log(500.0), n))
+    rtol = np.exp(rng.uniform(np.log(1e-9), np.log(1e-6), n))
+    return dict(rhs="loghalo", tableau="tsit5", y0=y0, theta=np.stack([v0, q, rc]),
+                t0=0.0, t1=t1, rtol=rtol, atol=rtol.copy(), t_out=None)
+
+
+def predicted_cost(w):
+    """Heuristic cost of each trajectory for longest-first queue order:
+    span times rtol^(-1/5) (a 5th-order method's steps per unit time)."""
+    span = np.broadcast_to(np.asarray(w["t1"], float) - np.asarray(w["t0"], float),
+                           (w["y0"].shape[1],))
+    rtol = np.broadcast_to(np.asarray(w["rtol"], float), span.shape)
+    return span * rtol ** (-0.2)
+
+
+def orbits_gradient(n=100_000, seed=3):
+    """As ``orbits_forward`` with t_end = 100, final state only, plus seeded
+    targets T_i ~ N(0, 1)^3 for the loss sum_i |x_i(100) - T_i|^2."""
+    w = orbits_forward(n, seed)
+    rng = _rng(seed + 1000)
+    w.update(t1=100.0, t_out=None, targets=rng.normal(0.0, 1.0, (3, n)))
+    return w
+
+
+def spin_precession(n=1_000_000, seed=4, n_grad=20_000):
+    """Binaries: q ~ U[0.1, 1], chi1, chi2 ~ U[0, 1], isotropic unit spins,
+    Lhat = z_hat; integrate in v = r^(-1/2) from r = 1000 to r = 10 with
+    Verner 7 at rtol = atol = 3.16e-9; 32 nodes at r_k = 1000 * 10^(-2k/31)."""
+    rng = _rng(seed)
+    q = rng.uniform(0.1, 1.0, n)
+    chi1 = rng.uniform(0.0, 1.0, n)
+    chi2 = rng.uniform(0.0, 1.0, n)
+    s1 = rng.normal(size=(3, n))
+    s1 /= np.linalg.norm(s1, axis=0)
+    s2 = rng.normal(size=(3, n))
+    s2 /= np.linalg.norm(s2, axis=0)
+    y0 = np.zeros((9, n))
+    y0[2] = 1.0
+    y0[3:6] = s1
+    y0[6:9] = s2
+    r_nodes = 1000.0 * 10.0 ** (-2.0 * np.arange(32) / 31.0)
+    return dict(rhs="spinprec", tableau="verner7", y0=y0, theta=np.stack([q, chi1, chi2]),
+                t0=1000.0 ** -0.5, t1=10.0 ** -0.5, rtol=3.16e-9, atol=3.16e-9,
+                t_out=r_nodes ** -0.5, n_grad=n_grad)
+
+
+def quintessence(n=10_000, seed=5, dense=False, omega_r=9.0e-5):
+    """Thawing quintessence: lambda ~ U[0, 1.5], Omega_m ~ U[0.28, 0.34],
+    Omega_r fixed; field at rest at z = 50; amplitude a0 = 1 - Omega_m -
+    Omega_r (the frozen-field value); Dopri5 at rtol 1.78e-4, atol = 1e-3 rtol;
+    nodes at 7 redshifts uniform in ln(1+z) on [0.3, 2.33] (dense variant: 64
+    on [0, 2.5]), stored as N = -ln(1+z) in increasing order."""
+    rng = _rng(seed)
+    lam = rng.uniform(0.0, 1.5, n)
+    om = rng.uniform(0.28, 0.34, n)
+    orad = np.full(n, omega_r)
+    a0 = 1.0 - om - orad
+    if dense:
+        z = np.expm1(np.linspace(np.log(3.5), 0.0, 64))
+    else:
+        z = np.expm1(np.linspace(np.log(3.33), np.log(1.3), 7))
+    return dict(rhs="quint", tableau="dopri5", y0=np.zeros((3, n)),
+                theta=np.stack([a0, lam, om, orad]), t0=-np.log(51.0), t1=0.0,
+                rtol=1.78e-4, atol=1.78e-7, t_out=-np.log1p(z), z_nodes=z)

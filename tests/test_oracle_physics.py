@@ -1,0 +1,215 @@
+"""Closed forms and invariants that pin the oracle's right-hand sides and its
+integration together.
+
+Logarithmic halo (eq:loghalo): circular in-plane orbits stay circular; energy
+and L_z are conserved (Section "Stellar streams").  Kepler: Kepler's equation.
+Quintessence (eq:de-model, eq:de-rhs): matter-only and cosmological-constant
+distances.  Spin precession (eq:prec-spins .. eq:prec-rr): unit lengths are
+conserved, a non-spinning binary only rotates its spins about a fixed L at the
+rate of eq:prec-omega divided by eq:prec-rr, and with chi2 = 0 the angle between
+L and S1 is conserved.
+"""
+import mpmath as mp
+import numpy as np
+import pytest
+from scipy.optimize import brentq
+
+from paper_2609_28458_amd import inputs
+
+TIGHT = dict(rtol=1e-12, atol=1e-12)
+
+
+def test_loghalo_circular_orbit(orc):
+    v0, q, rc = 1.0, 0.9, 0.1
+    R = np.array([0.5, 1.0, 1.7])
+    vc = v0 * R / np.sqrt(R * R + rc * rc)
+    y0 = np.zeros((6, 3))
+    y0[0] = R
+    y0[4] = vc
+    tk = np.linspace(1.0, 30.0, 12)
+    o = orc.solve("loghalo", "tsit5", y0, np.array([v0, q, rc]), 0.0, 30.0, 1e-12, 1e-12, tk)
+    Om = vc / R
+    x = R[None, :] * np.cos(Om[None, :] * tk[:, None])
+    y = R[None, :] * np.sin(Om[None, :] * tk[:, None])
+    np.testing.assert_allclose(o["y_out"][0], x, atol=1e-8)
+    np.testing.assert_allclose(o["y_out"][1], y, atol=1e-8)
+    np.testing.assert_allclose(o["y_out"][2], 0.0, atol=1e-14)
+
+
+def _energy_lz(y, v0, q, rc):
+    D = rc * rc + y[0] ** 2 + y[1] ** 2 + y[2] ** 2 / q ** 2
+    E = 0.5 * (y[3] ** 2 + y[4] ** 2 + y[5] ** 2) + 0.5 * v0 * v0 * np.log(D)
+    Lz = y[0] * y[4] - y[1] * y[3]
+    return E, Lz
+
+
+@pytest.mark.parametrize("tab", ["dopri5", "tsit5", "verner7"])
+def test_loghalo_conservation(orc, tab):
+    w = inputs.orbits_forward(n=64, seed=21)
+    th = w["theta"]
+    o = orc.solve(w["rhs"], tab, w["y0"], th, 0.0, 50.0, 1e-10, 1e-10, w["t_out"])
+    E0, L0 = _energy_lz(w["y0"], *th)
+    E, L = _energy_lz(o["y_out"], *th)
+    assert np.max(np.abs(E - E0[None, :])) < 1e-7
+    assert np.max(np.abs(L - L0[None, :])) < 1e-7
+    assert np.all(o["status"] == 0)
+
+
+def test_kepler_closed_form(orc):
+    """Eccentric orbit (a = 1, e = 0.6, mu = 1) from periapsis: positions from
+    Kepler's equation E - e sin E = t."""
+    a, e, mu = 1.0, 0.6, 1.0
+    y0 = np.array([[a * (1 - e)], [0.0], [0.0], [np.sqrt(mu * (1 + e) / (a * (1 - e)))]])
+    tk = np.linspace(0.3, 20.0, 25)
+    o = orc.solve("kepler", "verner7", y0, np.array([mu]), 0.0, 20.0, 1e-13, 1e-13, tk)
+    for k, t in enumerate(tk):
+        M = t  # mean motion sqrt(mu / a^3) = 1
+        Ek = brentq(lambda E: E - e * np.sin(E) - M, M - 2, M + 2, xtol=1e-15)
+        x = a * (np.cos(Ek) - e)
+        y = a * np.sqrt(1 - e * e) * np.sin(Ek)
+        assert abs(o["y_out"][0, k, 0] - x) < 1e-9 and abs(o["y_out"][1, k, 0] - y) < 1e-9
+    # energy, angular momentum and the Runge--Lenz vector
+    Y = o["y_out"][:, :, 0]
+    r = np.hypot(Y[0], Y[1])
+    En = 0.5 * (Y[2] ** 2 + Y[3] ** 2) - mu / r
+    Lz = Y[0] * Y[3] - Y[1] * Y[2]
+    Ax = Y[3] * Lz - mu * Y[0] / r
+    np.testing.assert_allclose(En, -mu / (2 * a), atol=1e-11)
+    np.testing.assert_allclose(Lz, np.sqrt(mu * a * (1 - e * e)), atol=1e-11)
+    np.testing.assert_allclose(Ax, mu * e, atol=1e-10)
+
+
+def _quint_E(y, th, N):
+    a0, lam, om, orad = th
+    pot = a0 * np.exp(-lam * y[0])
+    return np.sqrt((om * np.exp(-3 * N) + orad * np.exp(-4 * N) + pot) / (1 - y[1] ** 2 / 6))
+
+
+def test_quint_matter_only(orc):
+    """Omega_m = 1, Omega_r = a0 = 0: D_M = 2(1 - (1+z)^-1/2), D_H = (1+z)^-3/2."""
+    z = np.expm1(np.linspace(np.log(3.5), 0.05, 20))
+    N = -np.log1p(z)
+    th = np.array([0.0, 0.7, 1.0, 0.0])
+    o = orc.solve("quint", "dopri5", np.zeros((3, 1)), th, -np.log(51.0), 0.0, 1e-11, 1e-13, N)
+    I = o["y_out"][2, :, 0]
+    DM = o["y_final"][2, 0] - I
+    np.testing.assert_allclose(DM, 2 * (1 - (1 + z) ** -0.5), rtol=0, atol=1e-10)
+    DH = 1.0 / _quint_E(o["y_out"][:, :, 0], th, N)
+    np.testing.assert_allclose(DH, (1 + z) ** -1.5, rtol=1e-12)
+    np.testing.assert_allclose(o["y_out"][:2], 0.0, atol=0)
+
+
+def test_quint_cosmological_constant(orc):
+    """lambda = 0: the field never moves and D_M(z) = int_0^z dz / E(z) with
+    E^2 = Om (1+z)^3 + Or (1+z)^4 + a0."""
+    om, orad = 0.31, 9e-5
+    a0 = 1 - om - orad
+    z = np.array([0.3, 0.8, 1.5, 2.33])
+    N = np.sort(-np.log1p(z))
+    th = np.array([a0, 0.0, om, orad])
+    o = orc.solve("quint", "verner7", np.zeros((3, 1)), th, -np.log(51.0), 0.0, 1e-13, 1e-13, N)
+    DM = o["y_final"][2, 0] - o["y_out"][2, :, 0]
+    for k, Nk in enumerate(N):
+        zk = np.expm1(-Nk)
+        ref = mp.quad(lambda x: 1 / mp.sqrt(om * (1 + x) ** 3 + orad * (1 + x) ** 4 + a0), [0, zk])
+        assert abs(DM[k] - float(ref)) < 1e-11
+    np.testing.assert_allclose(o["y_out"][:2], 0.0, atol=0)
+
+
+def test_quint_thawing_energy_density_decreases(orc):
+    """A rolling field has w > -1, so rho_phi = E^2 u^2 / 6 + v(phi) falls
+    (eq:de-w, eq:de-rho), and the frozen amplitude leaves E(0) < 1."""
+    w = inputs.quintessence(n=32, seed=22)
+    o = orc.solve(w["rhs"], "tsit5", w["y0"], w["theta"], w["t0"], 0.0, 1e-10, 1e-12,
+                  np.linspace(w["t0"], 0.0, 40)[1:])
+    Y = o["y_out"]
+    Nn = np.linspace(w["t0"], 0.0, 40)[1:]
+    a0, lam = w["theta"][0], w["theta"][1]
+    E = _quint_E(Y, w["theta"][:, None, :], Nn[:, None])
+    rho = E ** 2 * Y[1] ** 2 / 6 + a0[None, :] * np.exp(-lam[None, :] * Y[0])
+    moving = lam > 0.05
+    assert np.all(np.diff(rho[:, moving], axis=0) <= 1e-14)
+    E0 = _quint_E(o["y_final"], w["theta"], 0.0)
+    assert np.all(E0[moving] < 1.0)
+    wstate = (E ** 2 * Y[1] ** 2 / 6 - a0 * np.exp(-lam * Y[0])) / rho
+    assert np.all(wstate[:, moving] >= -1.0)
+
+
+def _prec(orc, y0, th, K=None, tol=1e-12, tab="verner7"):
+    v0 = 100.0 ** -0.5
+    v1 = 10.0 ** -0.5
+    return orc.solve("spinprec", tab, y0, th, v0, v1, tol, tol, K)
+
+
+def test_precession_unit_lengths(orc):
+    w = inputs.spin_precession(n=32, seed=23)
+    v_nodes = np.linspace(100.0 ** -0.5, 10.0 ** -0.5, 9)[1:]
+    o = _prec(orc, w["y0"], w["theta"], v_nodes, tol=1e-10)
+    for s in range(3):
+        nrm = np.linalg.norm(o["y_out"][3 * s:3 * s + 3], axis=0)
+        assert np.max(np.abs(nrm - 1.0)) < 1e-8
+    assert np.all(o["status"] == 0)
+
+
+def test_precession_nonspinning_rotation(orc):
+    """chi1 = chi2 = 0: L stays fixed and S_j rotates about it by
+    phi_j = int Omega_j / (dv/dt) dv (eq:prec-omega over eq:prec-rr)."""
+    q = 0.6
+    s1 = np.array([0.6, 0.0, 0.8])
+    s2 = np.array([0.0, 0.8, -0.6])
+    y0 = np.concatenate([[0, 0, 1], s1, s2]).reshape(9, 1)
+    o = _prec(orc, y0, np.array([q, 0.0, 0.0]), tol=1e-13)
+    eta = q / (1 + q) ** 2
+    b2 = -(743 / 336 + 11 * eta / 4)
+    b3 = 4 * mp.pi
+    b4 = 34103 / 18144 + 13661 * eta / 2016 + 59 * eta * eta / 18
+
+    def phi(c):
+        return float(mp.quad(lambda v: c * eta * v ** 5 / 2 /
+                             (mp.mpf(32) / 5 * eta * v ** 9 * (1 + b2 * v * v + b3 * v ** 3
+                                                                 + b4 * v ** 4)),
+                             [100 ** -0.5, 10 ** -0.5]))
+
+    np.testing.assert_allclose(o["y_final"][:3, 0], [0, 0, 1], atol=1e-14)
+    for sv, c, off in ((s1, 4 + 3 * q, 3), (s2, 4 + 3 / q, 6)):
+        ph = phi(c)
+        rot = np.array([sv[0] * np.cos(ph) - sv[1] * np.sin(ph),
+                        sv[0] * np.sin(ph) + sv[1] * np.cos(ph), sv[2]])
+        np.testing.assert_allclose(o["y_final"][off:off + 3, 0], rot, atol=1e-9)
+
+
+def test_precession_single_spin_tilt_conserved(orc):
+    """chi2 = 0: Omega_1 is parallel to L, so L.S1 is conserved."""
+    w = inputs.spin_precession(n=16, seed=24)
+    th = w["theta"].copy()
+    th[2] = 0.0
+    o = _prec(orc, w["y0"], th, tol=1e-11)
+    c0 = np.sum(w["y0"][:3] * w["y0"][3:6], axis=0)
+    c1 = np.sum(o["y_final"][:3] * o["y_final"][3:6], axis=0)
+    np.testing.assert_allclose(c1, c0, atol=2e-9)
+
+
+def test_precession_effective_spin_conserved(orc):
+    """xi = (1+q) S1 L.S1 + (1 + 1/q) S2 L.S2 is conserved by eq:prec-spins,
+    eq:prec-L and eq:prec-omega for any radiation reaction."""
+    w = inputs.spin_precession(n=16, seed=25)
+    o = _prec(orc, w["y0"], w["theta"], tol=1e-11)
+    q, c1, c2 = w["theta"]
+    S1 = c1 / (1 + q) ** 2
+    S2 = c2 * q * q / (1 + q) ** 2
+
+    def xi(y):
+        return ((1 + q) * S1 * np.sum(y[:3] * y[3:6], axis=0) +
+                (1 + 1 / q) * S2 * np.sum(y[:3] * y[6:9], axis=0))
+
+    np.testing.assert_allclose(xi(o["y_final"]), xi(w["y0"]), atol=1e-9)
+
+
+def test_tight_reference_self_consistency(orc):
+    """The tight reference (Verner 7 at 1e-13) agrees with a run ten times looser
+    to a tenth of the orbit budget (Appendix "References, tolerances and
+    timing"), here far better."""
+    w = inputs.orbits_forward(n=32, seed=26)
+    a = orc.solve(w["rhs"], "verner7", w["y0"], w["theta"], 0.0, 50.0, 1e-13, 1e-13, w["t_out"])
+    b = orc.solve(w["rhs"], "verner7", w["y0"], w["theta"], 0.0, 50.0, 1e-12, 1e-12, w["t_out"])
+    assert np.max(np.abs(a["y_out"] - b["y_out"])) < 1e-5 / 10
