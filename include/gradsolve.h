@@ -1,0 +1,231 @@
+/*
+ * gradsolve -- ensemble solve and discrete-adjoint gradients of many small
+ * independent ODE systems on one AMD Instinct MI355X (gfx950).
+ *
+ * The problem is the paper's ensemble initial-value problem (Section "The
+ * ensemble problem", eq:ivp): n independent systems dy_i/dt = f(t, y_i,
+ * theta_i), y_i(t0_i) = y0_i, each read at output times t_k.  Every
+ * trajectory is integrated by an explicit Runge--Kutta pair with its own
+ * adaptive step (Appendix "Runge--Kutta steps and error control": eq:rk,
+ * eq:errnorm, eq:controller), outputs inside a step come from the dense
+ * polynomial or, for Verner 7, a shortened step (eq:dense), and gradients of
+ * scalar losses are the exact derivative of the discrete solution with the
+ * accepted steps held fixed (Appendix "Derivatives", eq:stage-sens; here
+ * computed in reverse mode, the transpose of that recursion).
+ *
+ * Conventions shared by every entry point:
+ *  - All array pointers are DEVICE pointers owned by the caller.  The
+ *    library never allocates or frees memory in these calls, so they can be
+ *    captured in a HIP graph.  Arrays are float64 or int32 as declared.
+ *  - Layouts are structure-of-arrays with the trajectory index fastest:
+ *    a state is [d][n], outputs are [d][K][n].
+ *  - A "stride" of 0 broadcasts one value (or vector) to all trajectories.
+ *  - Calls are asynchronous on `stream` (a hipStream_t; NULL = the null
+ *    stream).  Argument errors are detected on the host before anything is
+ *    launched and returned as a gs_status; nothing is launched then.
+ *  - Numerical failures of single trajectories are NOT call errors: the
+ *    call returns GS_OK and status[i] carries a gs_traj_status.
+ *  - Nothing throws across this boundary.
+ */
+#ifndef GRADSOLVE_H
+#define GRADSOLVE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum gs_status {
+  GS_OK = 0,
+  GS_ERR_INVALID = 1,     /* bad argument (null pointer, size, layout, order) */
+  GS_ERR_UNSUPPORTED = 2, /* valid request this build does not implement     */
+  GS_ERR_WORKSPACE = 3,   /* workspace missing or smaller than required      */
+  GS_ERR_HIP = 4,         /* a HIP runtime call failed                       */
+  GS_ERR_NO_TAPE = 5      /* gradient requested but the solve kept no tape   */
+} gs_status;
+
+/* Per-trajectory outcome written to status[i]. */
+typedef enum gs_traj_status {
+  GS_TRAJ_OK = 0,
+  GS_TRAJ_MAX_STEPS = 1,     /* max_steps attempts without reaching t1        */
+  GS_TRAJ_DT_UNDERFLOW = 2,  /* |h| < 16 eps max(|t|, 1)                      */
+  GS_TRAJ_NONFINITE = 3,     /* non-finite y0 or state, or 50 NaN rejections  */
+  GS_TRAJ_TAPE_OVERFLOW = 4, /* reached t1, but more checkpoints than the
+                                capacity: the trajectory cannot be replayed   */
+  GS_TRAJ_BAD_INPUT = 5      /* t1 < t0, rtol <= 0, atol < 0, or output nodes
+                                not non-decreasing within [t0, t1]; checked
+                                on the device, nothing integrated, outputs NaN */
+} gs_traj_status;
+
+/* Runge--Kutta pairs (Section "Adaptive integration"). */
+typedef enum gs_tableau_id {
+  GS_DOPRI5 = 0,  /* Dormand & Prince 5(4), FSAL, 4th-order continuous output */
+  GS_TSIT5 = 1,   /* Tsitouras 5(4), FSAL, 4th-order interpolant              */
+  GS_VERNER7 = 2  /* Verner 7(6), 10 stages, outputs by shortened steps       */
+} gs_tableau_id;
+
+/* Right-hand sides; each fixes d (state size) and p (parameter count). */
+typedef enum gs_rhs_id {
+  GS_RHS_HARMONIC = 0, /* d=2 (x, v), p=1 (omega)                           */
+  GS_RHS_KEPLER = 1,   /* d=4 (x, y, vx, vy), p=1 (mu)                      */
+  GS_RHS_LOGHALO = 2,  /* d=6 (x, v), p=3 (v0, q, rc); eq:loghalo           */
+  GS_RHS_SPINPREC = 3, /* d=9 (L, S1, S2 unit vectors) in v, p=3 (q, chi1,
+                          chi2); eq:prec-spins, eq:prec-L, eq:prec-omega,
+                          eq:prec-rr with 2PN radiation reaction              */
+  GS_RHS_QUINT = 4     /* d=3 (phi, u, I) in N = ln a, p=4 (a0, lambda,
+                          Omega_m, Omega_r); eq:de-model, eq:de-rhs          */
+} gs_rhs_id;
+
+/* How trajectories are handed to lanes. */
+typedef enum gs_schedule {
+  GS_SCHED_QUEUE = 0, /* persistent grid; lanes retire and refill from an
+                         atomic work queue                                   */
+  GS_SCHED_STATIC = 1 /* one lane per trajectory, no refill (a lane waits for
+                         the slowest lane of its wavefront)                  */
+} gs_schedule;
+
+/* Step-size controller, eq:controller generalised to PI form:
+ *   h_new = h * min(alpha_max, max(alpha_min,
+ *                    safety * err^(-beta1) * err_prev^(beta2)))
+ * with err_prev the (floored at 1e-4) norm of the last accepted step.
+ * beta1 <= 0 selects 1/nu; beta2 = 0 is the paper's I controller. */
+typedef struct gs_controller {
+  double safety;    /* paper: "< 1"; 0.9 by default                 */
+  double alpha_min; /* paper: 0.2                                   */
+  double alpha_max; /* paper: 5                                     */
+  double beta1;
+  double beta2;
+} gs_controller;
+
+/* One ensemble solve.  Sizes: d and p must equal those of `rhs`. */
+typedef struct gs_solve_args {
+  int32_t rhs;     /* gs_rhs_id                                             */
+  int32_t tableau; /* gs_tableau_id                                         */
+  int64_t n;       /* trajectories (0 allowed: nothing is launched)         */
+  int32_t d, p;
+
+  const double* y0;      /* [d][n]                                          */
+  const double* theta;   /* [p][theta_stride] (stride 0: shared [p] vector)  */
+  int64_t theta_stride;  /* 0 or n                                          */
+  const double* t0;      /* [t_stride]; t1[i] >= t0[i]                      */
+  const double* t1;
+  int64_t t_stride;      /* 0 or 1                                          */
+  const double* rtol;    /* [tol_stride], > 0                               */
+  const double* atol;    /* [tol_stride], >= 0                              */
+  int64_t tol_stride;    /* 0 or 1                                          */
+
+  int32_t K;             /* output nodes per trajectory (0 = none)          */
+  const double* t_out;   /* [K][t_out_stride], non-decreasing in k, each in
+                            [t0, t1] of its trajectory                      */
+  int64_t t_out_stride;  /* 0 or n                                          */
+
+  double* y_out;         /* [d][K][n], or NULL when K == 0                  */
+  double* y_final;       /* [d][n]                                          */
+  int32_t* n_accepted;   /* [n]                                             */
+  int32_t* n_rejected;   /* [n]                                             */
+  int32_t* status;       /* [n] gs_traj_status                              */
+
+  int64_t max_steps;     /* attempts per trajectory; <= 0: 10^7             */
+  double h0;             /* > 0: first step; <= 0: Hairer-Norsett-Wanner
+                            starting-step rule                              */
+  gs_controller ctrl;
+
+  /* Gradient tape: a checkpoint (t, h, err_prev, y, f(t, y)) every
+     ckpt_every accepted steps, ckpt_capacity of them per trajectory.
+     ckpt_every = 0 keeps no tape (no gradient, no dense query). */
+  int32_t ckpt_every;
+  int32_t ckpt_capacity;
+
+  /* Launch shape (0 = choose automatically). */
+  int32_t schedule;      /* gs_schedule                                     */
+  int32_t block;         /* lanes per workgroup: 64, 128, 192 or 256        */
+  int32_t grid;          /* workgroups of the persistent grid               */
+  int32_t refill;        /* refill a wavefront once this many lanes idle,
+                            1..64                                           */
+  const int64_t* order;  /* [n] queue order (a permutation of 0..n-1), or
+                            NULL for 0, 1, ..., n-1                         */
+
+  void* workspace;       /* device memory, >= gs_workspace_bytes(args),
+                            256-byte aligned.  Bytes 16..23 hold a uint64
+                            count of adjoint segment replays that did not
+                            reproduce the next checkpoint bit-exactly
+                            (diagnostic; reset by each gs_solve_vjp).      */
+  size_t workspace_bytes;
+  void* stream;          /* hipStream_t                                     */
+} gs_solve_args;
+
+/* Cotangents for gs_solve_vjp.  R independent scalar losses share one replay:
+ * for each r, ybar_out[r] = dL_r/dy(t_k) and ybar_final[r] = dL_r/dy(t1). */
+typedef struct gs_vjp_args {
+  int32_t R;                /* 1 <= R <= 8                                  */
+  const double* ybar_out;   /* [R][d][K][n] or NULL                         */
+  const double* ybar_final; /* [R][d][n] or NULL                            */
+  double* y0bar;            /* [R][d][n]  out: dL_r/dy0                     */
+  double* thetabar;         /* [R][p][n]  out: dL_r/dtheta_i per trajectory;
+                               for shared theta the caller sums over n      */
+  int32_t block;            /* 0 = automatic                                */
+  int32_t grid;             /* 0 = automatic                                */
+  void* stream;             /* hipStream_t                                  */
+} gs_vjp_args;
+
+/* Fill a gs_solve_args with defaults: the paper's controller (safety 0.9,
+ * alpha 0.2 / 5, I control), automatic h0, max_steps 10^7, queue schedule,
+ * automatic launch shape, no tape.  Pointers are zeroed. */
+void gs_default_args(gs_solve_args* args);
+
+/* Bytes of workspace `args` needs: the work-queue counters, the tape
+ * (n * ckpt_capacity checkpoints of 3 + 2d doubles) and the adjoint's
+ * per-lane replay scratch (ckpt_every steps of 2 + d doubles per lane).
+ * Returns 0 for an invalid `args`. */
+size_t gs_workspace_bytes(const gs_solve_args* args);
+
+/* Integrate every trajectory from t0 to t1 (eq:rk .. eq:dense), writing
+ * y_out at the nodes, y_final, step counts and status, and, when
+ * ckpt_every > 0, the checkpoint tape into the workspace. */
+gs_status gs_solve(const gs_solve_args* args);
+
+/* Reverse-mode derivative of the discrete solution of the last gs_solve call
+ * made with the same `fwd` arguments and workspace (tape required): for each
+ * trajectory and loss r,
+ *   y0bar[r]    = sum_k ybar_out[r][k] S_y0(t_k)    + ybar_final[r] S_y0(t1)
+ *   thetabar[r] = sum_k ybar_out[r][k] S_theta(t_k) + ybar_final[r] S_theta(t1)
+ * where S are the forward sensitivities of eq:stage-sens along the accepted
+ * steps.  Segments between checkpoints are recomputed bit-identically.
+ * Trajectories whose status is not GS_TRAJ_OK get NaN cotangents. */
+gs_status gs_solve_vjp(const gs_solve_args* fwd, const gs_vjp_args* vjp);
+
+/* Solution at arbitrary times t_query [Q][n] (each in [t0, t1]) from the tape
+ * of the last gs_solve with `fwd` (eq:dense; replay from the nearest
+ * checkpoint, or from t0 when no tape was kept).  y_query is [d][Q][n]. */
+gs_status gs_dense_eval(const gs_solve_args* fwd, int32_t Q, const double* t_query,
+                        double* y_query, void* stream);
+
+/* Evaluate the right-hand side and its vector-Jacobian product at m points:
+ * f = f(t, y, theta) and, for kbar given, ybar = J_y^T kbar,
+ * thetabar = J_theta^T kbar.  y, f, ybar, kbar [d][m]; theta, thetabar [p][m];
+ * t [m].  ybar, thetabar, kbar may all be NULL. */
+gs_status gs_rhs_eval(int32_t rhs, int64_t m, const double* t, const double* y,
+                      const double* theta, double* f, const double* kbar, double* ybar,
+                      double* thetabar, void* stream);
+
+/* Graph of one gs_solve: the queue reset and the solve kernel captured once
+ * into a hipGraph and replayed with gs_graph_launch on any stream.  The graph
+ * keeps the pointers of `args`. */
+typedef struct gs_graph gs_graph;
+gs_status gs_graph_create(const gs_solve_args* args, gs_graph** out);
+gs_status gs_graph_launch(gs_graph* g, void* stream);
+void gs_graph_destroy(gs_graph* g);
+
+/* Static description of a status code. */
+const char* gs_status_string(gs_status s);
+
+/* Version of this library, e.g. "0.1.0". */
+const char* gs_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GRADSOLVE_H */

@@ -175,7 +175,7 @@ def solve(rhs, tableau, y0, theta, t0, t1, rtol, atol, t_out=None, *, max_steps=
     P.safety, P.alpha_min, P.alpha_max = safety, alpha_min, alpha_max
     P.beta1, P.beta2 = beta1, beta2
     P.no_grow_after_reject = 1 if no_grow_after_reject else 0
-    P.nthreads = nthreads or os.cpu_count() or 1
+    P.nthreads = nthreads or min(os.cpu_count() or 1, 16)
     P.m, P.cols, P.S_out, P.S_final = m, _ptr(cols), _ptr(S_out), _ptr(S_final)
     P.h_cap, P.h_rec, P.h_replay, P.n_replay = int(h_cap), _ptr(h_rec), _ptr(hr), _ptr(nr)
     rc = lib().gso_solve(C.byref(P))

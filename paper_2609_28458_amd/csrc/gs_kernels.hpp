@@ -1,0 +1,955 @@
+// Device side of the ensemble solver: one trajectory per wavefront lane.
+//
+// Every lane keeps its trajectory's state y, the stage derivatives k_j and
+// the controller scalars in VGPRs; all loops over stages and components are
+// unrolled at compile time so no array ever leaves registers.  The steps of
+// the method follow the paper's Appendix "Numerical details":
+//   stages and update          eq:rk
+//   scaled RMS error norm      eq:errnorm
+//   accept iff norm <= 1, new step from the (PI-generalised) controller
+//                              eq:controller
+//   outputs inside a step      eq:dense (polynomial), or a shortened step
+//                              from the start of the step for Verner 7
+// The derivative is the transpose of eq:stage-sens (reverse mode, steps held
+// fixed), computed by replaying each checkpointed segment.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <type_traits>
+
+#include "gs_rhs.hpp"
+#include "gs_tableaux.hpp"
+
+namespace gs {
+
+// ---------------------------------------------------------------------------
+// Compile-time loops.
+template <int I, int N, class Fn>
+__device__ __forceinline__ void sfor_impl(Fn& fn) {
+  if constexpr (I < N) {
+    fn(std::integral_constant<int, I>{});
+    sfor_impl<I + 1, N>(fn);
+  }
+}
+template <int N, class Fn>
+__device__ __forceinline__ void sfor(Fn&& fn) {
+  sfor_impl<0, N>(fn);
+}
+// Descending: N-1, ..., 0.
+template <int I, class Fn>
+__device__ __forceinline__ void rfor_impl(Fn& fn) {
+  if constexpr (I >= 0) {
+    fn(std::integral_constant<int, I>{});
+    rfor_impl<I - 1>(fn);
+  }
+}
+template <int N, class Fn>
+__device__ __forceinline__ void rfor(Fn&& fn) {
+  rfor_impl<N - 1>(fn);
+}
+
+// std::min / std::max semantics (a NaN in the second argument is ignored the
+// same way on every path).
+__device__ __forceinline__ double dmin(double a, double b) { return (b < a) ? b : a; }
+__device__ __forceinline__ double dmax(double a, double b) { return (a < b) ? b : a; }
+
+constexpr int ST_OK = 0, ST_MAX_STEPS = 1, ST_DT_UNDERFLOW = 2, ST_NONFINITE = 3,
+              ST_TAPE_OVERFLOW = 4, ST_BAD_INPUT = 5;
+
+// Everything a kernel needs; a plain copy of the C-ABI arguments.
+struct Params {
+  int64_t n;
+  const double* y0;
+  const double* theta;
+  int64_t theta_stride;
+  const double* t0;
+  const double* t1;
+  int64_t t_stride;
+  const double* rtol;
+  const double* atol;
+  int64_t tol_stride;
+  int32_t K;
+  const double* t_out;
+  int64_t t_out_stride;
+  double* y_out;
+  double* y_final;
+  int32_t* n_acc;
+  int32_t* n_rej;
+  int32_t* status;
+  int64_t max_steps;
+  double h0;
+  double safety, amin, amax, beta1, beta2;
+  int32_t ckpt_every;
+  int32_t ckpt_cap;
+  double* tape;                 // [n][ckpt_cap][3 + 2 d]
+  unsigned long long* counters; // [0] forward queue, [1] adjoint queue, [2] replay mismatches
+  const int64_t* order;
+  int32_t refill;
+  int32_t sched_static;
+};
+
+struct VjpParams {
+  int32_t R;           // losses handled by this launch (<= template R)
+  int32_t r0;          // first loss index of this launch
+  int32_t R_total;     // leading dimension of the cotangent arrays
+  const double* ybar_out;
+  const double* ybar_final;
+  double* y0bar;
+  double* thetabar;
+  double* scratch;     // [lanes][ckpt_every][2 + d]
+};
+
+__device__ __forceinline__ double node_time(const Params& P, int kk, int64_t i) {
+  return P.t_out_stride ? P.t_out[(int64_t)kk * P.t_out_stride + i] : P.t_out[kk];
+}
+
+// Per-trajectory inputs.
+template <class F>
+struct Inputs {
+  double th[F::P];
+  typename F::Par par;
+  double t0, t1, rtol, atol;
+};
+
+template <class F>
+__device__ __forceinline__ void load_inputs(const Params& P, int64_t i, Inputs<F>& in,
+                                            double (&y)[F::D]) {
+#pragma unroll
+  for (int c = 0; c < F::D; ++c) y[c] = P.y0[(int64_t)c * P.n + i];
+#pragma unroll
+  for (int c = 0; c < F::P; ++c)
+    in.th[c] = P.theta_stride ? P.theta[(int64_t)c * P.theta_stride + i] : P.theta[c];
+  in.par = F::prep(in.th);
+  in.t0 = P.t0[P.t_stride ? i : 0];
+  in.t1 = P.t1[P.t_stride ? i : 0];
+  in.rtol = P.rtol[P.tol_stride ? i : 0];
+  in.atol = P.atol[P.tol_stride ? i : 0];
+}
+
+// Checks that cannot be done on the host without reading device memory.
+template <class F>
+__device__ __forceinline__ bool inputs_valid(const Params& P, int64_t i, const Inputs<F>& in) {
+  bool ok = (in.t1 >= in.t0) && (in.rtol > 0.0) && (in.atol >= 0.0);
+  double prev = in.t0;
+  for (int kk = 0; kk < P.K; ++kk) {
+    const double tk = node_time(P, kk, i);
+    ok = ok && (tk >= prev) && (tk <= in.t1);
+    prev = tk;
+  }
+  return ok;
+}
+
+// Starting step of Hairer, Norsett & Wanner (1993, Sec. II.4); the paper
+// gives none.  RMS norms scaled by atol + rtol |y0|; one extra evaluation.
+template <class TB, class F>
+__device__ double initial_step(const Inputs<F>& in, const double (&y)[F::D],
+                               const double (&f0)[F::D]) {
+  constexpr int D = F::D;
+  const double span = in.t1 - in.t0;
+  double d0 = 0.0, d1 = 0.0;
+#pragma unroll
+  for (int c = 0; c < D; ++c) {
+    const double sc = in.atol + fabs(y[c]) * in.rtol;
+    d0 += (y[c] / sc) * (y[c] / sc);
+    d1 += (f0[c] / sc) * (f0[c] / sc);
+  }
+  d0 = sqrt(d0 / D);
+  d1 = sqrt(d1 / D);
+  double h0 = (d0 < 1e-5 || d1 < 1e-5) ? 1e-6 : 0.01 * d0 / d1;
+  h0 = dmin(h0, span);
+  double y1[D], f1[D];
+#pragma unroll
+  for (int c = 0; c < D; ++c) y1[c] = y[c] + h0 * f0[c];
+  F::f(in.t0 + h0, y1, in.par, f1);
+  double d2 = 0.0;
+#pragma unroll
+  for (int c = 0; c < D; ++c) {
+    const double sc = in.atol + fabs(y[c]) * in.rtol;
+    const double r = (f1[c] - f0[c]) / sc;
+    d2 += r * r;
+  }
+  d2 = sqrt(d2 / D) / h0;
+  const double h1 = (d1 <= 1e-15 && d2 <= 1e-15) ? dmax(1e-6, h0 * 1e-3)
+                                                 : pow(0.01 / dmax(d1, d2), 1.0 / TB::ORDER);
+  return dmin(dmin(100.0 * h0, h1), span);
+}
+
+// Stages 2..s of one step of length h from (t, y) with k[0] = f(t, y)
+// given (eq:rk).  Returns y+ in yn.  For FSAL pairs the last stage point is
+// y+ itself (its row of A is b), so yn costs nothing extra.
+template <class TB, class F>
+__device__ __forceinline__ void rk_stages(const typename F::Par& par, double t, double h,
+                                          const double (&y)[F::D], double (&k)[TB::S][F::D],
+                                          double (&yn)[F::D]) {
+  constexpr int S = TB::S, D = F::D;
+  sfor<S - 1>([&](auto J1) {
+    constexpr int j = decltype(J1)::value + 1;
+    double Y[D];
+#pragma unroll
+    for (int c = 0; c < D; ++c) {
+      double acc = 0.0;
+      sfor<j>([&](auto L) {
+        constexpr int l = decltype(L)::value;
+        constexpr double a = TB::A(j, l);
+        if constexpr (a != 0.0) acc = fma(a, k[l][c], acc);
+      });
+      Y[c] = fma(h, acc, y[c]);
+    }
+    F::f(t + TB::C(j) * h, Y, par, k[j]);
+    if constexpr (TB::FSAL && j == S - 1) {
+#pragma unroll
+      for (int c = 0; c < D; ++c) yn[c] = Y[c];
+    }
+  });
+  if constexpr (!TB::FSAL) {
+#pragma unroll
+    for (int c = 0; c < D; ++c) {
+      double acc = 0.0;
+      sfor<S>([&](auto J) {
+        constexpr int j = decltype(J)::value;
+        constexpr double b = TB::B(j);
+        if constexpr (b != 0.0) acc = fma(b, k[j][c], acc);
+      });
+      yn[c] = fma(h, acc, y[c]);
+    }
+  }
+}
+
+// Scaled RMS norm (eq:errnorm) of e = h sum_j (b_j - bhat_j) k_j.
+template <class TB, class F>
+__device__ __forceinline__ double error_norm(double h, const double (&y)[F::D],
+                                             const double (&yn)[F::D],
+                                             const double (&k)[TB::S][F::D], double rtol,
+                                             double atol) {
+  constexpr int D = F::D;
+  double acc2 = 0.0;
+#pragma unroll
+  for (int c = 0; c < D; ++c) {
+    double e = 0.0;
+    sfor<TB::S>([&](auto J) {
+      constexpr int j = decltype(J)::value;
+      constexpr double w = TB::E(j);
+      if constexpr (w != 0.0) e = fma(w, k[j][c], e);
+    });
+    e *= h;
+    const double sc = fma(rtol, dmax(fabs(y[c]), fabs(yn[c])), atol);
+    const double r = e / sc;
+    acc2 = fma(r, r, acc2);
+  }
+  return sqrt(acc2 / D);
+}
+
+// Value at t + sigma h inside an accepted step: the polynomial of eq:dense,
+// or (Verner 7) a shortened step of length sigma h from (t, y) reusing k[0].
+template <class TB, class F>
+__device__ __forceinline__ void dense_value(const typename F::Par& par, double t, double h,
+                                            double sigma, const double (&y)[F::D],
+                                            const double (&k)[TB::S][F::D],
+                                            double (&out)[F::D]) {
+  constexpr int S = TB::S, D = F::D;
+  if constexpr (TB::POLY_DENSE) {
+    double w[S];
+    sfor<S>([&](auto J) {
+      constexpr int j = decltype(J)::value;
+      double acc = 0.0;
+      rfor<TB::DEG>([&](auto Q) {
+        constexpr int q = decltype(Q)::value;
+        acc = fma(acc, sigma, TB::Bs(j, q));
+      });
+      w[j] = acc * sigma;
+    });
+#pragma unroll
+    for (int c = 0; c < D; ++c) {
+      double acc = 0.0;
+#pragma unroll
+      for (int j = 0; j < S; ++j) acc = fma(w[j], k[j][c], acc);
+      out[c] = fma(h, acc, y[c]);
+    }
+  } else {
+    double ks[S][D];
+#pragma unroll
+    for (int c = 0; c < D; ++c) ks[0][c] = k[0][c];
+    rk_stages<TB, F>(par, t, sigma * h, y, ks, out);
+  }
+}
+
+// Controller of eq:controller (PI form, beta2 = 0 is the paper's I form).
+__device__ __forceinline__ double step_factor(const Params& P, double b1, double en,
+                                              double err_prev, bool finite) {
+  if (!finite) return P.amin;
+  if (en == 0.0) return P.amax;
+  double raw = P.safety * pow(en, -b1);
+  if (P.beta2 != 0.0) raw *= pow(err_prev, P.beta2);
+  return dmin(P.amax, dmax(P.amin, raw));
+}
+
+__device__ __forceinline__ bool underflow(double h, double t) {
+  return fabs(h) < 16.0 * 2.220446049250313e-16 * dmax(fabs(t), 1.0);
+}
+
+// Integration state of one lane.
+template <class TB, class F>
+struct Traj {
+  static constexpr int S = TB::S, D = F::D;
+  Inputs<F> in;
+  double y[D];
+  double k[S][D];
+  double t, h, err_prev;
+  int32_t nacc, nrej, nanrun;
+};
+
+// Outcome of one attempt.
+struct Attempt {
+  bool accepted;
+  bool finished;
+  int32_t status;
+  double t_start, h_used, t_new;
+};
+
+// One step attempt with everything the controller does after it.  Node
+// output is done by the caller through `on_accept`, which sees the state
+// before the update (t, y, k of the step) together with y+ and t_new.
+template <class TB, class F, class OnAccept>
+__device__ __forceinline__ Attempt attempt(const Params& P, Traj<TB, F>& s, double b1,
+                                           OnAccept&& on_accept) {
+  constexpr int S = TB::S, D = F::D;
+  Attempt a;
+  a.accepted = false;
+  a.finished = false;
+  a.status = ST_OK;
+  a.t_start = s.t;
+  bool last = false;
+  double hh = s.h;
+  if (s.t + hh >= s.in.t1) {
+    hh = s.in.t1 - s.t;
+    last = true;
+  }
+  a.h_used = hh;
+  double yn[D];
+  rk_stages<TB, F>(s.in.par, s.t, hh, s.y, s.k, yn);
+  const double en = error_norm<TB, F>(hh, s.y, yn, s.k, s.in.rtol, s.in.atol);
+  const bool finite = (en == en) && (en < __builtin_inf());
+  const double factor = step_factor(P, b1, en, s.err_prev, finite);
+  if (finite && en <= 1.0) {
+    a.accepted = true;
+    a.t_new = last ? s.in.t1 : s.t + hh;
+    on_accept(s, hh, a.t_new, yn);
+    s.t = a.t_new;
+    bool fin = true;
+#pragma unroll
+    for (int c = 0; c < D; ++c) {
+      s.y[c] = yn[c];
+      fin = fin && (yn[c] == yn[c]) && (fabs(yn[c]) < __builtin_inf());
+    }
+    s.err_prev = dmax(en, 1e-4);
+    ++s.nacc;
+    if constexpr (TB::FSAL) {
+#pragma unroll
+      for (int c = 0; c < D; ++c) s.k[0][c] = s.k[S - 1][c];
+    } else {
+      F::f(s.t, s.y, s.in.par, s.k[0]);
+    }
+    s.nanrun = 0;
+    if (!fin) {
+      a.finished = true;
+      a.status = ST_NONFINITE;
+      return a;
+    }
+    if (last) {
+      a.finished = true;
+      return a;
+    }
+  } else {
+    ++s.nrej;
+    if (!finite) {
+      if (++s.nanrun >= 50) {
+        a.finished = true;
+        a.status = ST_NONFINITE;
+        return a;
+      }
+    } else {
+      s.nanrun = 0;
+    }
+  }
+  s.h = hh * factor;
+  if (underflow(s.h, s.t)) {
+    a.finished = true;
+    a.status = ST_DT_UNDERFLOW;
+  }
+  return a;
+}
+
+template <class TB, class F>
+__device__ __forceinline__ double* tape_record(const Params& P, int64_t i, int c) {
+  constexpr int REC = 3 + 2 * F::D;
+  return P.tape + ((int64_t)i * P.ckpt_cap + c) * REC;
+}
+
+template <class TB, class F>
+__device__ __forceinline__ void write_checkpoint(const Params& P, int64_t i, int c,
+                                                 const Traj<TB, F>& s) {
+  double* r = tape_record<TB, F>(P, i, c);
+  r[0] = s.t;
+  r[1] = s.h;
+  r[2] = s.err_prev;
+#pragma unroll
+  for (int j = 0; j < F::D; ++j) {
+    r[3 + j] = s.y[j];
+    r[3 + F::D + j] = s.k[0][j];
+  }
+}
+
+template <class TB, class F>
+__device__ __forceinline__ void read_checkpoint(const Params& P, int64_t i, int c,
+                                                Traj<TB, F>& s) {
+  const double* r = tape_record<TB, F>(P, i, c);
+  s.t = r[0];
+  s.h = r[1];
+  s.err_prev = r[2];
+#pragma unroll
+  for (int j = 0; j < F::D; ++j) {
+    s.y[j] = r[3 + j];
+    s.k[0][j] = r[3 + F::D + j];
+  }
+  s.nanrun = 0;
+}
+
+__device__ __forceinline__ uint64_t lanemask_lt() {
+  const int lane = threadIdx.x & 63;
+  return lane == 0 ? 0ull : (~0ull >> (64 - lane));
+}
+
+// ---------------------------------------------------------------------------
+// Forward solve.  Persistent grid: each lane holds one trajectory; when at
+// least `refill` lanes of a wavefront are idle, one atomic fetches that many
+// queue positions and the idle lanes take them (ballot + prefix count).  In
+// static mode lane g integrates trajectory g and is never refilled.
+template <class TB, class F>
+__global__ void __launch_bounds__(256) solve_kernel(Params P) {
+  constexpr int D = F::D;
+  const double b1 = P.beta1 > 0.0 ? P.beta1 : 1.0 / TB::ORDER;
+  Traj<TB, F> s;
+  int64_t idx = -1;
+  int32_t kp = 0;
+  bool live = false, overflow = false;
+  bool queue_empty = P.sched_static != 0;  // wave-uniform
+  const int lane = threadIdx.x & 63;
+
+  // Write the final results of the lane's trajectory and free the lane.
+  auto finish = [&](int32_t st) {
+    for (; kp < P.K; ++kp) {
+#pragma unroll
+      for (int c = 0; c < D; ++c)
+        P.y_out[((int64_t)c * P.K + kp) * P.n + idx] = __builtin_nan("");
+    }
+#pragma unroll
+    for (int c = 0; c < D; ++c) P.y_final[(int64_t)c * P.n + idx] = s.y[c];
+    P.n_acc[idx] = s.nacc;
+    P.n_rej[idx] = s.nrej;
+    P.status[idx] = (st == ST_OK && overflow) ? ST_TAPE_OVERFLOW : st;
+    live = false;
+  };
+
+  // Take trajectory i: load, validate, first evaluation, starting step.
+  auto start = [&](int64_t i) {
+    idx = i;
+    live = true;
+    kp = 0;
+    overflow = false;
+    s.nacc = s.nrej = s.nanrun = 0;
+    s.err_prev = 1.0;
+    load_inputs<F>(P, i, s.in, s.y);
+    s.t = s.in.t0;
+    bool fin = true;
+#pragma unroll
+    for (int c = 0; c < D; ++c) fin = fin && (s.y[c] == s.y[c]) && (fabs(s.y[c]) < __builtin_inf());
+    if (!inputs_valid<F>(P, i, s.in)) {
+      finish(ST_BAD_INPUT);
+      return;
+    }
+    // Nodes at t0 take y0.
+    while (kp < P.K && node_time(P, kp, i) <= s.in.t0) {
+#pragma unroll
+      for (int c = 0; c < D; ++c) P.y_out[((int64_t)c * P.K + kp) * P.n + i] = s.y[c];
+      ++kp;
+    }
+    if (!fin) {
+      finish(ST_NONFINITE);
+      return;
+    }
+    if (!(s.in.t1 > s.in.t0)) {
+      finish(ST_OK);
+      return;
+    }
+    F::f(s.t, s.y, s.in.par, s.k[0]);
+    s.h = P.h0 > 0.0 ? dmin(P.h0, s.in.t1 - s.in.t0) : initial_step<TB, F>(s.in, s.y, s.k[0]);
+    if (P.ckpt_every > 0) {
+      if (P.ckpt_cap > 0)
+        write_checkpoint<TB, F>(P, i, 0, s);
+      else
+        overflow = true;
+    }
+  };
+
+  if (P.sched_static) {
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g < P.n) start(g);
+  }
+
+  for (;;) {
+    if (!queue_empty) {
+      const uint64_t idle = __ballot(!live);
+      const int nidle = __popcll(idle);
+      if (nidle >= P.refill) {
+        unsigned long long base = 0;
+        if (lane == 0) base = atomicAdd(P.counters, (unsigned long long)nidle);
+        base = __shfl(base, 0);
+        if (base + (unsigned long long)nidle >= (unsigned long long)P.n) queue_empty = true;
+        if (!live) {
+          const unsigned long long pos = base + __popcll(idle & lanemask_lt());
+          if (pos < (unsigned long long)P.n) {
+            const int64_t id = P.order ? P.order[pos] : (int64_t)pos;
+            if (id >= 0 && id < P.n) start(id);  // a bad permutation entry is skipped
+          }
+        }
+      }
+    }
+    if (__ballot(live) == 0) {
+      if (queue_empty) break;
+      continue;
+    }
+    if (live) {
+      if ((int64_t)s.nacc + s.nrej >= P.max_steps) {
+        finish(ST_MAX_STEPS);
+        continue;
+      }
+      const Attempt a = attempt<TB, F>(
+          P, s, b1,
+          [&](const Traj<TB, F>& st, double hh, double t_new, const double (&yn)[D]) {
+            while (kp < P.K) {
+              const double tq = node_time(P, kp, idx);
+              if (!(tq <= t_new)) break;
+              double out[D];
+              if (tq == t_new) {
+#pragma unroll
+                for (int c = 0; c < D; ++c) out[c] = yn[c];
+              } else {
+                dense_value<TB, F>(st.in.par, st.t, hh, (tq - st.t) / hh, st.y, st.k, out);
+              }
+#pragma unroll
+              for (int c = 0; c < D; ++c) P.y_out[((int64_t)c * P.K + kp) * P.n + idx] = out[c];
+              ++kp;
+            }
+          });
+      if (a.finished) {
+        finish(a.status);
+      } else if (a.accepted && P.ckpt_every > 0 && (s.nacc % P.ckpt_every) == 0) {
+        const int c = s.nacc / P.ckpt_every;
+        if (c < P.ckpt_cap)
+          write_checkpoint<TB, F>(P, idx, c, s);
+        else
+          overflow = true;
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// A stage can receive a cotangent only through y+ (b_j != 0), a later stage
+// (a_ij != 0) or a dense output; this decides it at compile time for the
+// first two routes.
+template <class TB>
+__host__ __device__ constexpr bool stage_feeds_step(int j) {
+  if (TB::B(j) != 0.0) return true;
+  for (int i = j + 1; i < TB::S; ++i)
+    if (TB::A(i, j) != 0.0) return true;
+  return false;
+}
+
+// Reverse of one explicit RK step of length h from (t, y) (the transpose of
+// eq:stage-sens with h fixed).  lam[r] enters as the cotangent of y+ and
+// leaves as the cotangent of y; thb[r] accumulates the parameter cotangent.
+// An interior output of a polynomial-dense pair (has_node) adds
+// h b_j(sigma) g to the stage cotangents and g to the cotangent of y.
+template <class TB, class F, int R>
+__device__ __forceinline__ void reverse_step(const Inputs<F>& in, double t, double h,
+                                             const double (&y)[F::D], double (&lam)[R][F::D],
+                                             double (&thb)[R][F::P], bool has_node, double sg,
+                                             const double (&gq)[R][F::D]) {
+  constexpr int S = TB::S, D = F::D;
+  // Recompute the stage points Y_j.
+  double Y[S][D];
+  {
+    double k[S][D];
+#pragma unroll
+    for (int c = 0; c < D; ++c) Y[0][c] = y[c];
+    F::f(t, y, in.par, k[0]);
+    sfor<S - 1>([&](auto J1) {
+      constexpr int j = decltype(J1)::value + 1;
+      if (stage_feeds_step<TB>(j) || (TB::POLY_DENSE && has_node)) {
+#pragma unroll
+        for (int c = 0; c < D; ++c) {
+          double acc = 0.0;
+          sfor<j>([&](auto L) {
+            constexpr int l = decltype(L)::value;
+            constexpr double a = TB::A(j, l);
+            if constexpr (a != 0.0) acc = fma(a, k[l][c], acc);
+          });
+          Y[j][c] = fma(h, acc, y[c]);
+        }
+        if constexpr (j < S - 1) F::f(t + TB::C(j) * h, Y[j], in.par, k[j]);
+      }
+    });
+  }
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    double kb[S][D];
+    double yb[D];
+    sfor<S>([&](auto J) {
+      constexpr int j = decltype(J)::value;
+      constexpr double b = TB::B(j);
+#pragma unroll
+      for (int c = 0; c < D; ++c) kb[j][c] = (h * b) * lam[r][c];
+    });
+#pragma unroll
+    for (int c = 0; c < D; ++c) yb[c] = lam[r][c];
+    if constexpr (TB::POLY_DENSE) {
+      if (has_node) {
+        sfor<S>([&](auto J) {
+          constexpr int j = decltype(J)::value;
+          double w = 0.0;
+          rfor<TB::DEG>([&](auto Q) {
+            constexpr int qq = decltype(Q)::value;
+            w = fma(w, sg, TB::Bs(j, qq));
+          });
+          w *= sg * h;
+#pragma unroll
+          for (int c = 0; c < D; ++c) kb[j][c] = fma(w, gq[r][c], kb[j][c]);
+        });
+#pragma unroll
+        for (int c = 0; c < D; ++c) yb[c] += gq[r][c];
+      }
+    }
+    rfor<S>([&](auto J) {
+      constexpr int j = decltype(J)::value;
+      if (stage_feeds_step<TB>(j) || (TB::POLY_DENSE && has_node)) {
+        double ybj[D];
+        F::vjp(t + TB::C(j) * h, Y[j], in.th, in.par, kb[j], ybj, thb[r]);
+#pragma unroll
+        for (int c = 0; c < D; ++c) yb[c] += ybj[c];
+        sfor<j>([&](auto L) {
+          constexpr int l = decltype(L)::value;
+          constexpr double a = TB::A(j, l);
+          if constexpr (a != 0.0) {
+#pragma unroll
+            for (int c = 0; c < D; ++c) kb[l][c] = fma(h * a, ybj[c], kb[l][c]);
+          }
+        });
+      }
+    });
+#pragma unroll
+    for (int c = 0; c < D; ++c) lam[r][c] = yb[c];
+  }
+}
+
+// Discrete adjoint.  For each trajectory, segments between checkpoints are
+// processed last to first: replay the segment from its checkpoint (the same
+// attempt function as the forward, so the same accepted steps), keep
+// (t_n, h_n, y_n) of every accepted step in per-lane scratch, then run the
+// reverse steps backwards, injecting output-node cotangents where they fall.
+template <class TB, class F, int R>
+__global__ void __launch_bounds__(256) vjp_kernel(Params P, VjpParams V) {
+  constexpr int D = F::D, NP = F::P;
+  constexpr int SREC = 2 + D;
+  const double b1 = P.beta1 > 0.0 ? P.beta1 : 1.0 / TB::ORDER;
+  const int lane = threadIdx.x & 63;
+  const int64_t slot = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double* scr = V.scratch + slot * (int64_t)P.ckpt_every * SREC;
+  for (;;) {
+    // One trajectory per lane per round; every lane of the wave asks together.
+    unsigned long long base = 0;
+    if (lane == 0) base = atomicAdd(P.counters + 1, 64ull);
+    base = __shfl(base, 0);
+    if (base >= (unsigned long long)P.n) break;
+    const unsigned long long pos = base + lane;
+    if (pos >= (unsigned long long)P.n) continue;
+    const int64_t i = (int64_t)pos;
+    Traj<TB, F> s;
+    double yfinal_unused[D];
+    load_inputs<F>(P, i, s.in, yfinal_unused);
+    const int32_t st = P.status[i];
+    const int32_t N = P.n_acc[i];
+    double lam[R][D], thb[R][NP];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+#pragma unroll
+      for (int c = 0; c < D; ++c)
+        lam[r][c] = (V.ybar_final && r < V.R)
+                        ? V.ybar_final[((int64_t)(V.r0 + r) * D + c) * P.n + i]
+                        : 0.0;
+#pragma unroll
+      for (int c = 0; c < NP; ++c) thb[r][c] = 0.0;
+    }
+    auto gbar = [&](int r, int c, int kk) -> double {
+      return (V.ybar_out && r < V.R)
+                 ? V.ybar_out[(((int64_t)(V.r0 + r) * D + c) * P.K + kk) * P.n + i]
+                 : 0.0;
+    };
+    int kp = P.K - 1;
+    bool replay_ok = true;
+    if (st == ST_OK) {
+      const int nseg = (N + P.ckpt_every - 1) / P.ckpt_every;
+      for (int cseg = nseg - 1; cseg >= 0; --cseg) {
+        const int m = min(P.ckpt_every, N - cseg * P.ckpt_every);
+        read_checkpoint<TB, F>(P, i, cseg, s);
+        s.nacc = cseg * P.ckpt_every;
+        s.nrej = 0;
+        int j = 0;
+        while (j < m) {
+          const Attempt a = attempt<TB, F>(
+              P, s, b1, [&](const Traj<TB, F>& sb, double hh, double, const double (&)[D]) {
+                double* rec = scr + (int64_t)j * SREC;
+                rec[0] = sb.t;
+                rec[1] = hh;
+#pragma unroll
+                for (int c = 0; c < D; ++c) rec[2 + c] = sb.y[c];
+              });
+          if (a.accepted) ++j;
+          if (a.finished && j < m) break;  // cannot happen on a faithful replay
+        }
+        if (j < m) {
+          atomicAdd(P.counters + 2, 1ull);
+          replay_ok = false;
+          break;
+        }
+        // Bit-exact replay check against the next checkpoint.
+        if (cseg + 1 < nseg && cseg + 1 < P.ckpt_cap) {
+          const double* nxt = tape_record<TB, F>(P, i, cseg + 1);
+          bool same = true;
+#pragma unroll
+          for (int c = 0; c < D; ++c) same = same && (nxt[3 + c] == s.y[c]);
+          if (!same) atomicAdd(P.counters + 2, 1ull);
+        }
+        for (int jj = m - 1; jj >= 0; --jj) {
+          const double* rec = scr + (int64_t)jj * SREC;
+          const double tn = rec[0], hn = rec[1];
+          double yn[D];
+#pragma unroll
+          for (int c = 0; c < D; ++c) yn[c] = rec[2 + c];
+          const bool last_step = (cseg * P.ckpt_every + jj) == N - 1;
+          const double t_new = last_step ? s.in.t1 : tn + hn;
+          // Nodes at the end of the step read y+ itself.
+          while (kp >= 0 && node_time(P, kp, i) == t_new) {
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+#pragma unroll
+              for (int c = 0; c < D; ++c) lam[r][c] += gbar(r, c, kp);
+            --kp;
+          }
+          double gq[R][D];
+          if constexpr (TB::POLY_DENSE) {
+            // The step's own cotangent together with its last interior node;
+            // further interior nodes of the same step enter with a zero
+            // cotangent for y+ and their results are summed.
+            bool first = true;
+            do {
+              const bool has = kp >= 0 && node_time(P, kp, i) > tn;
+              double sg = 0.0;
+              if (has) {
+                sg = (node_time(P, kp, i) - tn) / hn;
+#pragma unroll
+                for (int r = 0; r < R; ++r)
+#pragma unroll
+                  for (int c = 0; c < D; ++c) gq[r][c] = gbar(r, c, kp);
+                --kp;
+              } else {
+#pragma unroll
+                for (int r = 0; r < R; ++r)
+#pragma unroll
+                  for (int c = 0; c < D; ++c) gq[r][c] = 0.0;
+              }
+              if (first) {
+                reverse_step<TB, F, R>(s.in, tn, hn, yn, lam, thb, has, sg, gq);
+                first = false;
+              } else {
+                double lz[R][D];
+#pragma unroll
+                for (int r = 0; r < R; ++r)
+#pragma unroll
+                  for (int c = 0; c < D; ++c) lz[r][c] = 0.0;
+                reverse_step<TB, F, R>(s.in, tn, hn, yn, lz, thb, true, sg, gq);
+#pragma unroll
+                for (int r = 0; r < R; ++r)
+#pragma unroll
+                  for (int c = 0; c < D; ++c) lam[r][c] += lz[r][c];
+              }
+            } while (kp >= 0 && node_time(P, kp, i) > tn);
+          } else {
+            // Shortened-step outputs: each one is a full step of length
+            // sigma h from the start of the step.
+            double lz[R][D];
+            while (kp >= 0 && node_time(P, kp, i) > tn) {
+              const double hq = ((node_time(P, kp, i) - tn) / hn) * hn;
+#pragma unroll
+              for (int r = 0; r < R; ++r)
+#pragma unroll
+                for (int c = 0; c < D; ++c) {
+                  lz[r][c] = gbar(r, c, kp);
+                  gq[r][c] = 0.0;
+                }
+              reverse_step<TB, F, R>(s.in, tn, hq, yn, lz, thb, false, 0.0, gq);
+#pragma unroll
+              for (int r = 0; r < R; ++r)
+#pragma unroll
+                for (int c = 0; c < D; ++c) lam[r][c] += lz[r][c];
+              --kp;
+            }
+            reverse_step<TB, F, R>(s.in, tn, hn, yn, lam, thb, false, 0.0, gq);
+          }
+        }
+      }
+      // Nodes at t0 read y0 directly.
+      while (kp >= 0) {
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+#pragma unroll
+          for (int c = 0; c < D; ++c) lam[r][c] += gbar(r, c, kp);
+        --kp;
+      }
+    }
+    const bool ok = (st == ST_OK) && replay_ok;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      if (r >= V.R) break;
+#pragma unroll
+      for (int c = 0; c < D; ++c)
+        V.y0bar[((int64_t)(V.r0 + r) * D + c) * P.n + i] = ok ? lam[r][c] : __builtin_nan("");
+#pragma unroll
+      for (int c = 0; c < NP; ++c)
+        V.thetabar[((int64_t)(V.r0 + r) * NP + c) * P.n + i] = ok ? thb[r][c] : __builtin_nan("");
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Dense query: y(t_q) for Q times per trajectory, by replaying from the last
+// checkpoint before t_q (or from t0 without a tape).
+template <class TB, class F>
+__global__ void __launch_bounds__(256) dense_kernel(Params P, int32_t Q, const double* tq_all,
+                                                    double* yq_all) {
+  constexpr int D = F::D;
+  const double b1 = P.beta1 > 0.0 ? P.beta1 : 1.0 / TB::ORDER;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= P.n) return;
+  Traj<TB, F> s;
+  double y0[D];
+  load_inputs<F>(P, i, s.in, y0);
+  const int32_t st = P.status[i];
+  const int32_t N = P.n_acc[i];
+  const bool tape = P.ckpt_every > 0;
+  const int nseg = tape ? min((N + P.ckpt_every - 1) / P.ckpt_every, P.ckpt_cap) : 0;
+  for (int q = 0; q < Q; ++q) {
+    const double tq = tq_all[(int64_t)q * P.n + i];
+    double out[D];
+    bool done = false;
+    if (st != ST_OK || !(tq >= s.in.t0) || !(tq <= s.in.t1)) {
+#pragma unroll
+      for (int c = 0; c < D; ++c) out[c] = __builtin_nan("");
+      done = true;
+    } else if (tq == s.in.t0) {
+#pragma unroll
+      for (int c = 0; c < D; ++c) out[c] = y0[c];
+      done = true;
+    }
+    if (!done) {
+      if (tape && nseg > 0) {
+        // Last checkpoint strictly before tq.
+        int lo = 0, hi = nseg - 1;
+        while (lo < hi) {
+          const int mid = (lo + hi + 1) / 2;
+          if (tape_record<TB, F>(P, i, mid)[0] < tq)
+            lo = mid;
+          else
+            hi = mid - 1;
+        }
+        read_checkpoint<TB, F>(P, i, lo, s);
+      } else {
+#pragma unroll
+        for (int c = 0; c < D; ++c) s.y[c] = y0[c];
+        s.t = s.in.t0;
+        s.err_prev = 1.0;
+        s.nanrun = 0;
+        F::f(s.t, s.y, s.in.par, s.k[0]);
+        s.h = P.h0 > 0.0 ? dmin(P.h0, s.in.t1 - s.in.t0) : initial_step<TB, F>(s.in, s.y, s.k[0]);
+      }
+      s.nacc = 0;
+      s.nrej = 0;
+      for (int guard = 0; guard < 100000000 && !done; ++guard) {
+        const Attempt a = attempt<TB, F>(
+            P, s, b1,
+            [&](const Traj<TB, F>& sb, double hh, double t_new, const double (&yn)[D]) {
+              if (tq <= t_new) {
+                if (tq == t_new) {
+#pragma unroll
+                  for (int c = 0; c < D; ++c) out[c] = yn[c];
+                } else {
+                  dense_value<TB, F>(sb.in.par, sb.t, hh, (tq - sb.t) / hh, sb.y, sb.k, out);
+                }
+                done = true;
+              }
+            });
+        if (a.finished && !done) {
+#pragma unroll
+          for (int c = 0; c < D; ++c) out[c] = __builtin_nan("");
+          done = true;
+        }
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < D; ++c) yq_all[((int64_t)c * Q + q) * P.n + i] = out[c];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Pointwise right-hand side and its VJP (for testing the hand-written
+// transposes against forward-mode derivatives).
+template <class F>
+__global__ void __launch_bounds__(256) rhs_kernel(int64_t m, const double* t, const double* y,
+                                                  const double* theta, double* f,
+                                                  const double* kbar, double* ybar,
+                                                  double* thetabar) {
+  constexpr int D = F::D, NP = F::P;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= m) return;
+  double yy[D], th[NP], ff[D];
+#pragma unroll
+  for (int c = 0; c < D; ++c) yy[c] = y[(int64_t)c * m + i];
+#pragma unroll
+  for (int c = 0; c < NP; ++c) th[c] = theta[(int64_t)c * m + i];
+  const typename F::Par par = F::prep(th);
+  F::f(t[i], yy, par, ff);
+  if (f) {
+#pragma unroll
+    for (int c = 0; c < D; ++c) f[(int64_t)c * m + i] = ff[c];
+  }
+  if (kbar && ybar && thetabar) {
+    double kb[D], yb[D], tb[NP];
+#pragma unroll
+    for (int c = 0; c < D; ++c) kb[c] = kbar[(int64_t)c * m + i];
+#pragma unroll
+    for (int c = 0; c < NP; ++c) tb[c] = 0.0;
+    F::vjp(t[i], yy, th, par, kb, yb, tb);
+#pragma unroll
+    for (int c = 0; c < D; ++c) ybar[(int64_t)c * m + i] = yb[c];
+#pragma unroll
+    for (int c = 0; c < NP; ++c) thetabar[(int64_t)c * m + i] = tb[c];
+  }
+}
+
+__global__ void reset_counters_kernel(unsigned long long* c, int n) {
+  if ((int)threadIdx.x < n) c[threadIdx.x] = 0ull;
+}
+
+}  // namespace gs

@@ -1,0 +1,91 @@
+"""The C-ABI library loads, exports every symbol include/gradsolve.h declares,
+and rejects bad arguments on the host before touching the GPU (these calls
+run without a GPU)."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from paper_2609_28458_amd import api
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "gradsolve.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"\b(gs_[a-z_]+)\s*\(", src)
+    return sorted(set(names))
+
+
+def test_header_symbols_exported():
+    names = declared_functions()
+    assert "gs_solve" in names and "gs_solve_vjp" in names and "gs_dense_eval" in names
+    lib = C.CDLL(api.LIB_PATH)
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(api.EXPORTS) == set(names)
+
+
+def test_struct_layout_matches_header():
+    # offsets the binding relies on: compare the ctypes size with the C size
+    # reported through the default-args call (the library zero-fills exactly
+    # sizeof(gs_solve_args) bytes, so a larger ctypes struct keeps a sentinel).
+    buf = (C.c_ubyte * (C.sizeof(api.gs_solve_args) + 64))()
+    for i in range(len(buf)):
+        buf[i] = 0xAB
+    api.lib().gs_default_args(C.cast(buf, C.POINTER(api.gs_solve_args)))
+    assert buf[C.sizeof(api.gs_solve_args)] == 0xAB
+    assert all(buf[i] != 0xAB or i >= C.sizeof(api.gs_solve_args) for i in range(len(buf)))
+    a = api.gs_default_args()
+    assert a.ctrl.safety == 0.9 and a.ctrl.alpha_min == 0.2 and a.ctrl.alpha_max == 5.0
+    assert a.max_steps == 10_000_000
+
+
+def _args(**kw):
+    a = api.gs_default_args()
+    a.rhs, a.tableau, a.n, a.d, a.p = 2, 0, 1000, 6, 3
+    for f in ("y0", "theta", "t0", "t1", "rtol", "atol", "y_final", "n_accepted",
+              "n_rejected", "status"):
+        setattr(a, f, 0x1000)
+    a.workspace = 0x100000
+    a.workspace_bytes = 1 << 30
+    for k, v in kw.items():
+        setattr(a, k, v)
+    return a
+
+
+@pytest.mark.parametrize("kw", [
+    dict(rhs=7), dict(tableau=3), dict(d=5), dict(p=4), dict(n=-1),
+    dict(y0=None), dict(theta_stride=5), dict(t_stride=2), dict(K=3),
+    dict(ckpt_every=-1), dict(ckpt_every=4, ckpt_capacity=0), dict(block=100),
+    dict(block=1024), dict(refill=65), dict(schedule=5),
+])
+def test_invalid_arguments_rejected(kw):
+    assert api.lib().gs_solve(C.byref(_args(**kw))) == 1
+
+
+def test_workspace_checks():
+    a = _args(workspace=None)
+    assert api.lib().gs_solve(C.byref(a)) == 3
+    a = _args(ckpt_every=8, ckpt_capacity=100)
+    need = api.gs_workspace_bytes(a)
+    # counters + tape (n * cap * (3 + 2d) doubles) + scratch (lanes * k * (2 + d))
+    assert need == 256 + 1000 * 100 * 15 * 8 + 1024 * 8 * 8 * 8
+    a.workspace_bytes = need - 1
+    assert api.lib().gs_solve(C.byref(a)) == 3
+    a = _args(workspace=0x100010)
+    assert api.lib().gs_solve(C.byref(a)) == 3
+
+
+def test_vjp_requires_tape():
+    a = _args()
+    v = api.gs_vjp_args(1, None, 0x1000, 0x1000, 0x1000, 0, 0, None)
+    assert api.lib().gs_solve_vjp(C.byref(a), C.byref(v)) == 5
+
+
+def test_status_strings():
+    for code in range(6):
+        assert api.lib().gs_status_string(code)
+    assert api.gs_version() == "0.1.0"
