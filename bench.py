@@ -1,0 +1,236 @@
+"""Benchmark: ensemble solve throughput on one MI355X.
+
+Headline workload (N = 1): the uneven batch of 100,000 orbits in the
+flattened logarithmic halo with per-orbit (v0, q, rc), t_end ~ logU[10, 500]
+and rtol ~ logU[1e-9, 1e-6] (atol = rtol), Tsit5, final states.  One step is
+one complete ensemble solve from device-resident inputs: the work-queue
+reset and the persistent solve kernel, captured once in a hipGraph and
+replayed.  `value` is solves per second.
+
+Also reported on the same line:
+  * accepted RK steps/s and step attempts/s of the headline run;
+  * the two other launch arms of the same batch (static one lane per
+    trajectory, and one launch per cost bucket);
+  * the grad/forward time ratio on the gradient workload (100,000 orbits to
+    t = 100, Dopri5 1e-8/1e-10, loss sum |x - T|^2): forward with tape plus
+    adjoint, over the forward without tape;
+  * roofline: algorithmic FP64 flops of the solve kernel per launch over its
+    measured duration, against the FP64 vector peak (the path is FP64 ALU
+    bound, not MFMA or HBM);
+  * cpu_baseline: the CPU oracle on a bounded sample of the same batch.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAK_FP64_VECTOR_TFLOPS = 78.6   # MI355X: 256 CU x 2.4 GHz x 128 FP64 flop/clk
+# Algorithmic FP64 flops of one step attempt (fma = 2, div / sqrt / pow = 1),
+# counted from the kernel's operations:
+#   Tsit5 stage sums 2 * 6 * (21 + 6) = 324, stage times 12, error weights
+#   2 * 6 * 7 + 6 = 90, norm 6 * 5 + 2 = 32, controller and clipping 5;
+#   log-halo right-hand side 13 per evaluation, 6 evaluations = 78.
+FLOPS_PER_ATTEMPT = {("tsit5", "loghalo"): 541, ("dopri5", "loghalo"): 535}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n", type=int, default=100_000)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-grad", action="store_true", help="skip the gradient ratio")
+    ap.add_argument("--no-arms", action="store_true", help="skip the static and bucket arms")
+    return ap.parse_args()
+
+
+def timed(fn, steps, warmup, torch):
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    start.record()
+    for _ in range(steps):
+        fn()
+    stop.record()
+    torch.cuda.synchronize()
+    return start.elapsed_time(stop) / steps  # ms per step
+
+
+def cpu_baseline(w, target_s=12.0):
+    """The oracle as it is, on this host's cores, on a bounded seeded sample."""
+    import oracle
+
+    threads = min(os.cpu_count() or 1, 16)
+    rng = np.random.default_rng(1234)
+    n = w["y0"].shape[1]
+
+    def run(m):
+        idx = np.sort(rng.choice(n, m, replace=False))
+        t = time.perf_counter()
+        o = oracle.solve(w["rhs"], w["tableau"], w["y0"][:, idx], w["theta"][:, idx], 0.0,
+                         w["t1"][idx], w["rtol"][idx], w["atol"][idx], nthreads=threads)
+        return time.perf_counter() - t, o
+
+    m = 400
+    dt, _ = run(m)
+    m = int(min(n, max(400, m * target_s / max(dt, 1e-3))))
+    dt, o = run(m)
+    return {"value": m / dt, "unit": "solves/s", "cores": threads, "kind": "oracle",
+            "sample": f"{m} seeded orbits of the same 100,000-orbit batch, "
+                      f"{int(o['n_accepted'].sum())} accepted steps, {dt:.1f} s wall"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} is not supported "
+              "(the ensemble shards trivially, but this build measures one device).",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    from paper_2609_28458_amd import api, inputs
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    api.lib()
+    dev_name = torch.cuda.get_device_name(0)
+
+    # ---- headline: persistent queue in a hipGraph, longest-first order --------------------
+    w = inputs.orbits_uneven(n=args.n)
+    n = w["y0"].shape[1]
+    prob = api.make_problem(w["rhs"], w["tableau"], w["y0"], w["theta"], w["t0"], w["t1"],
+                            w["rtol"], w["atol"])
+    order = np.argsort(-inputs.predicted_cost(w), kind="stable")
+    launch = api.Launch(schedule="queue", block=256, refill=16)
+    sol = api.Solution(prob, launch)
+    sol.set_order(order)
+    graph = api.Graph(sol)
+    ms = timed(lambda: graph.launch(), args.steps, args.warmup, torch)
+    nacc = int(sol.n_accepted.to(torch.int64).sum())
+    nrej = int(sol.n_rejected.to(torch.int64).sum())
+    attempts = nacc + nrej
+    max_att = int((sol.n_accepted + sol.n_rejected).max())
+    ok = bool((sol.status == 0).all())
+    log(f"[bench] {dev_name}: uneven batch n={n}: {ms:.3f} ms/solve, {attempts} attempts, "
+        f"max per orbit {max_att}, all ok={ok}")
+
+    # Kernel-only duration with HIP events on the launch stream (the graph's
+    # first node is a one-thread counter reset; the solve kernel dominates).
+    s = torch.cuda.current_stream()
+
+    def direct():
+        sol.args.stream = s.cuda_stream
+        api.gs_solve(sol.args)
+
+    ms_kernel = timed(direct, args.steps, 1, torch)
+    flops = attempts * FLOPS_PER_ATTEMPT[("tsit5", "loghalo")]
+    achieved = flops / (ms_kernel * 1e-3) / 1e12
+    roofline = {"bound": "alu", "achieved": round(achieved, 3),
+                "peak": PEAK_FP64_VECTOR_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(achieved / PEAK_FP64_VECTOR_TFLOPS, 4), "traffic": None,
+                "kernel": "gs::solve_kernel<Tsit5, LogHalo>",
+                "flops_per_attempt": FLOPS_PER_ATTEMPT[("tsit5", "loghalo")],
+                "attempts_per_launch": attempts, "ms_per_launch": round(ms_kernel, 4)}
+    # Critical path: the longest trajectory alone, at one attempt per lane-step.
+    out = {
+        "metric": "solves/s + accepted RK steps/s at fixed error; grad/forward time ratio",
+        "value": n / (ms * 1e-3),
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "orbits_uneven_100k", "n": n, "rhs": "loghalo",
+                   "tableau": "tsit5", "rtol": "logU[1e-9,1e-6]", "t_end": "logU[10,500]",
+                   "launch": "persistent queue, longest-first, hipGraph"},
+        "accepted_steps_per_s": nacc / (ms * 1e-3),
+        "attempts_per_s": attempts / (ms * 1e-3),
+        "max_attempts_one_orbit": max_att,
+        "device": dev_name,
+        "roofline": roofline,
+    }
+
+    # ---- the other two arms of the same batch -------------------------------------------
+    if not args.no_arms:
+        st = api.Solution(prob, api.Launch(schedule="static", block=256))
+        ms_static = timed(lambda: st.run(), max(3, args.steps // 4), 1, torch)
+        cost = inputs.predicted_cost(w)
+        qs = np.quantile(cost, np.linspace(0, 1, 9))
+        bucket_sols = []
+        for b in range(8):
+            sel = np.nonzero((cost >= qs[b]) & ((cost < qs[b + 1]) if b < 7 else True))[0]
+            wb = {k: (v[..., sel] if isinstance(v, np.ndarray) and v.shape[-1] == n else v)
+                  for k, v in w.items()}
+            pb = api.make_problem(wb["rhs"], wb["tableau"], wb["y0"], wb["theta"], wb["t0"],
+                                  wb["t1"], wb["rtol"], wb["atol"])
+            bucket_sols.append(api.Solution(pb, api.Launch(schedule="static", block=256)))
+
+        def buckets():
+            for bs in bucket_sols:
+                bs.run()
+
+        ms_buckets = timed(buckets, max(3, args.steps // 4), 1, torch)
+        out["arms_ms"] = {"persistent_graph": round(ms, 4), "static_one_lane_each":
+                          round(ms_static, 4), "eight_cost_buckets": round(ms_buckets, 4)}
+        log(f"[bench] arms: persistent {ms:.3f} ms, static {ms_static:.3f} ms, "
+            f"buckets {ms_buckets:.3f} ms")
+
+    # ---- gradient workload: grad/forward ratio --------------------------------------------
+    if not args.no_grad:
+        wg = inputs.orbits_gradient(n=args.n)
+        pg = api.make_problem(wg["rhs"], wg["tableau"], wg["y0"], wg["theta"], wg["t0"],
+                              wg["t1"], wg["rtol"], wg["atol"])
+        plain = api.Solution(pg, api.Launch(block=256))
+        ms_fwd = timed(lambda: plain.run(), max(3, args.steps // 4), 1, torch)
+        T = torch.as_tensor(wg["targets"], device="cuda")
+        best = None
+        for k in (8, 32, 128):
+            cap = int(plain.n_accepted.max()) // k + 2
+            taped = api.Solution(pg, api.Launch(block=256, ckpt_every=k, ckpt_capacity=cap))
+            ybf = torch.zeros((1, 6, pg.n), dtype=torch.float64, device="cuda")
+
+            def grad_step():
+                taped.run()
+                ybf[0, :3] = 2.0 * (taped.y_final[:3] - T)
+                api.solve_vjp(taped, ybar_final=ybf)
+
+            ms_g = timed(grad_step, max(3, args.steps // 4), 1, torch)
+            log(f"[bench] gradient k={k}: {ms_g:.3f} ms (forward {ms_fwd:.3f} ms)")
+            if best is None or ms_g < best[1]:
+                best = (k, ms_g)
+        out["grad"] = {"workload": "orbits_gradient_100k", "ms_forward": round(ms_fwd, 4),
+                       "ms_forward_tape_plus_vjp": round(best[1], 4), "ckpt_every": best[0]}
+        out["grad_forward_ratio"] = best[1] / ms_fwd
+
+    if not args.no_cpu:
+        cb = cpu_baseline(w)
+        out["cpu_baseline"] = cb
+        log(f"[bench] cpu oracle: {cb['value']:.1f} solves/s on {cb['cores']} threads")
+
+    print(json.dumps(out), flush=True)
+    graph.close()
+
+
+if __name__ == "__main__":
+    main()

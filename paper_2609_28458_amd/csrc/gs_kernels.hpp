@@ -426,8 +426,17 @@ __device__ __forceinline__ uint64_t lanemask_lt() {
 // least `refill` lanes of a wavefront are idle, one atomic fetches that many
 // queue positions and the idle lanes take them (ballot + prefix count).  In
 // static mode lane g integrates trajectory g and is never refilled.
+// Occupancy target of the forward kernel: the stage array k[S][D] dominates
+// the live registers; up to 63 doubles (126 VGPRs) two waves per SIMD fit in
+// the 512-entry register file without spilling, beyond that one.
 template <class TB, class F>
-__global__ void __launch_bounds__(256) solve_kernel(Params P) {
+struct FwdOccupancy {
+  static constexpr int waves = (TB::S * F::D > 63) ? 1 : 2;
+};
+
+template <class TB, class F>
+__global__ void __launch_bounds__(256)
+    __attribute__((amdgpu_waves_per_eu(FwdOccupancy<TB, F>::waves, 8))) solve_kernel(Params P) {
   constexpr int D = F::D;
   const double b1 = P.beta1 > 0.0 ? P.beta1 : 1.0 / TB::ORDER;
   Traj<TB, F> s;
@@ -788,25 +797,34 @@ __global__ void __launch_bounds__(256) vjp_kernel(Params P, VjpParams V) {
             } while (kp >= 0 && node_time(P, kp, i) > tn);
           } else {
             // Shortened-step outputs: each one is a full step of length
-            // sigma h from the start of the step.
-            double lz[R][D];
+            // sigma h from the start of the step, so its cotangent lands on
+            // y_n directly and is added after the step itself is reversed.
+            double lz[R][D], acc[R][D];
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+#pragma unroll
+              for (int c = 0; c < D; ++c) {
+                acc[r][c] = 0.0;
+                gq[r][c] = 0.0;
+              }
             while (kp >= 0 && node_time(P, kp, i) > tn) {
               const double hq = ((node_time(P, kp, i) - tn) / hn) * hn;
 #pragma unroll
               for (int r = 0; r < R; ++r)
 #pragma unroll
-                for (int c = 0; c < D; ++c) {
-                  lz[r][c] = gbar(r, c, kp);
-                  gq[r][c] = 0.0;
-                }
+                for (int c = 0; c < D; ++c) lz[r][c] = gbar(r, c, kp);
               reverse_step<TB, F, R>(s.in, tn, hq, yn, lz, thb, false, 0.0, gq);
 #pragma unroll
               for (int r = 0; r < R; ++r)
 #pragma unroll
-                for (int c = 0; c < D; ++c) lam[r][c] += lz[r][c];
+                for (int c = 0; c < D; ++c) acc[r][c] += lz[r][c];
               --kp;
             }
             reverse_step<TB, F, R>(s.in, tn, hn, yn, lam, thb, false, 0.0, gq);
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+#pragma unroll
+              for (int c = 0; c < D; ++c) lam[r][c] += acc[r][c];
           }
         }
       }

@@ -1,0 +1,204 @@
+"""GPU discrete adjoint (gs_solve_vjp) and dense queries (gs_dense_eval).
+
+On a fixed sequence of accepted steps the forward sensitivities of the
+oracle are the exact derivative of the discrete solution (Appendix
+"Derivatives", eq:stage-sens); the adjoint is the transpose of the same
+recursion, so cotangent . S from the oracle must equal the GPU VJP up to
+rounding.  Free central differences of the GPU forward pass (steps not held
+fixed) must agree to 1e-5 relative.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from gpu_util import oracle_solve  # noqa: E402
+from paper_2609_28458_amd import api, inputs  # noqa: E402
+from test_gpu_forward import CASES  # noqa: E402
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a GPU")
+    api.lib()
+
+
+def _problem(w, n=None, tableau=None):
+    sl = slice(None) if n is None else slice(0, n)
+    nall = w["y0"].shape[1]
+
+    def cut(x):
+        return np.asarray(x)[sl] if np.ndim(x) == 1 and np.size(x) == nall else x
+
+    th = w["theta"] if np.ndim(w["theta"]) == 1 else w["theta"][:, sl]
+    return api.make_problem(w["rhs"], tableau or w["tableau"], w["y0"][:, sl], th, cut(w["t0"]),
+                            cut(w["t1"]), cut(w["rtol"]), cut(w["atol"]), w.get("t_out"))
+
+
+def _solve_taped(prob, k=8, cap=None, **launch):
+    cap = cap or 4096
+    sol = api.solve(prob, api.Launch(ckpt_every=k, ckpt_capacity=cap, **launch))
+    torch.cuda.synchronize()
+    return sol
+
+
+def _fs_grad(o, d, ybar_out, ybar_final):
+    """cotangent . S from the oracle's forward sensitivities, per trajectory."""
+    g = np.einsum("jn,jcn->cn", ybar_final, o["S_final"])
+    if ybar_out is not None:
+        g += np.einsum("jkn,jckn->cn", ybar_out, o["S_out"])
+    return g[:d], g[d:]
+
+
+@pytest.mark.parametrize("tab", ["dopri5", "tsit5", "verner7"])
+@pytest.mark.parametrize("name,make", CASES, ids=[c[0] for c in CASES])
+def test_vjp_matches_oracle_sensitivities(orc, name, make, tab):
+    w = make(150)
+    w["tableau"] = tab
+    prob = _problem(w)
+    d, n, K = prob.d, prob.n, prob.K
+    p = api.NPARAM[prob.rhs]
+    rng = np.random.default_rng(11)
+    ybo = rng.normal(size=(1, d, K, n))
+    ybf = rng.normal(size=(1, d, n))
+    sol = _solve_taped(prob, k=5)
+    assert np.all(sol.status.cpu().numpy() == 0)
+    y0b, thb = api.solve_vjp(sol, ybar_final=ybf, ybar_out=ybo)
+    torch.cuda.synchronize()
+    assert sol.replay_mismatches() == 0
+    th = w["theta"] if np.ndim(w["theta"]) == 2 else np.repeat(
+        np.asarray(w["theta"])[:, None], n, axis=1)
+    o = oracle_solve(orc, {**w, "theta": th}, sens_cols=list(range(d + p)))
+    np.testing.assert_array_equal(sol.n_accepted.cpu().numpy(), o["n_accepted"])
+    gy, gt = _fs_grad(o, d, ybo[0], ybf[0])
+    G = np.concatenate([y0b[0].cpu().numpy(), thb[0].cpu().numpy()])
+    R = np.concatenate([gy, gt])
+    scale = np.maximum(np.abs(R).max(axis=0), 1.0)
+    err = np.abs(G - R) / scale
+    assert err.max() < 1e-8, (err.max(), np.unravel_index(err.argmax(), err.shape))
+
+
+def test_checkpoint_interval_does_not_change_the_gradient():
+    w = inputs.orbits_forward(n=200, seed=51)
+    prob = _problem(w)
+    rng = np.random.default_rng(12)
+    ybo = rng.normal(size=(1, 6, prob.K, 200))
+    ybf = rng.normal(size=(1, 6, 200))
+    ref = None
+    for k in (1, 3, 8, 32, 128):
+        sol = _solve_taped(prob, k=k)
+        y0b, thb = api.solve_vjp(sol, ybar_final=ybf, ybar_out=ybo)
+        torch.cuda.synchronize()
+        assert sol.replay_mismatches() == 0
+        got = (y0b.cpu().numpy(), thb.cpu().numpy())
+        if ref is None:
+            ref = got
+        else:
+            np.testing.assert_array_equal(got[0], ref[0])
+            np.testing.assert_array_equal(got[1], ref[1])
+
+
+def test_several_losses_share_one_replay():
+    w = inputs.spin_precession(n=96, seed=52)
+    w = {**w, "t0": 100 ** -0.5, "t_out": None}
+    prob = _problem(w)
+    rng = np.random.default_rng(13)
+    ybf = rng.normal(size=(3, 9, 96))
+    sol = _solve_taped(prob, k=16)
+    y0b, thb = api.solve_vjp(sol, ybar_final=ybf)
+    for r in range(3):
+        a, b = api.solve_vjp(sol, ybar_final=ybf[r:r + 1])
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(y0b[r].cpu().numpy(), a[0].cpu().numpy())
+        np.testing.assert_array_equal(thb[r].cpu().numpy(), b[0].cpu().numpy())
+
+
+def _loss_parts(sol, targets):
+    x = sol.y_final[:3].cpu().numpy()
+    return np.sum((x - targets) ** 2, axis=0)
+
+
+def test_gradient_config_full_size(orc):
+    """100,000 orbits to t = 100, loss sum |x(100) - T|^2: adjoint VJP with
+    respect to (v0, q, rc) and the initial conditions.  Checked on sampled
+    orbits against the oracle's forward sensitivities, and on the shared
+    parameters against free central differences of the GPU forward pass."""
+    w = inputs.orbits_gradient()
+    n = w["y0"].shape[1]
+    T = w["targets"]
+    prob = _problem(w)
+    sol = _solve_taped(prob, k=32, cap=256)
+    st = sol.status.cpu().numpy()
+    assert np.all(st == 0)
+    ybf = np.zeros((1, 6, n))
+    ybf[0, :3] = 2.0 * (sol.y_final[:3].cpu().numpy() - T)
+    y0b, thb = api.solve_vjp(sol, ybar_final=ybf)
+    torch.cuda.synchronize()
+    assert sol.replay_mismatches() == 0
+    y0b, thb = y0b[0].cpu().numpy(), thb[0].cpu().numpy()
+    # (a) oracle forward sensitivities on 300 sampled orbits
+    idx = np.sort(np.random.default_rng(8).choice(n, 300, replace=False))
+    o = oracle_solve(orc, w, idx, sens_cols=list(range(9)))
+    gy, gt = _fs_grad(o, 6, None, ybf[0][:, idx])
+    G = np.concatenate([y0b[:, idx], thb[:, idx]])
+    R = np.concatenate([gy, gt])
+    err = np.abs(G - R) / np.maximum(np.abs(R).max(axis=0), 1.0)
+    assert err.max() < 1e-8, err.max()
+    # (b) free central differences of the GPU forward pass in each shared
+    # parameter.  Where theta +- h changes a trajectory's accept/reject
+    # pattern its loss jumps by about the local error, which a 1e-6 quotient
+    # turns into noise; those trajectories are excluded and counted.
+    base_counts = (sol.n_accepted.cpu().numpy(), sol.n_rejected.cpu().numpy())
+    for c in range(3):
+        h = 1e-6
+        parts, same = [], (np.ones(n, bool))
+        for sgn in (+1, -1):
+            th = np.array(w["theta"], float)
+            th[c] += sgn * h
+            s2 = api.solve(_problem({**w, "theta": th}))
+            torch.cuda.synchronize()
+            parts.append(_loss_parts(s2, T))
+            same &= (s2.n_accepted.cpu().numpy() == base_counts[0])
+            same &= (s2.n_rejected.cpu().numpy() == base_counts[1])
+        fd = (parts[0] - parts[1]) / (2 * h)
+        excluded = int(n - same.sum())
+        assert excluded < 0.03 * n, excluded
+        g = thb[c]
+        rel = np.abs(fd[same] - g[same]) / np.maximum(np.abs(g[same]), 1e-3)
+        assert np.quantile(rel, 0.99) < 1e-5, np.quantile(rel, 0.99)
+        tot_fd, tot_g = fd[same].sum(), g[same].sum()
+        assert abs(tot_fd - tot_g) <= 1e-5 * abs(tot_g), (c, tot_fd, tot_g, excluded)
+
+
+def test_tape_overflow_is_reported():
+    w = inputs.orbits_forward(n=64, seed=53)
+    prob = _problem(w)
+    sol = _solve_taped(prob, k=4, cap=3)
+    st = sol.status.cpu().numpy()
+    assert np.all(st == 4)
+    y0b, thb = api.solve_vjp(sol, ybar_final=np.ones((1, 6, 64)))
+    assert np.all(np.isnan(y0b.cpu().numpy()))
+    # the solution itself is still complete
+    ref = api.solve(prob)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(sol.y_final.cpu().numpy(), ref.y_final.cpu().numpy())
+
+
+@pytest.mark.parametrize("tab", ["tsit5", "verner7"])
+@pytest.mark.parametrize("taped", [True, False])
+def test_dense_queries_match_oracle_nodes(orc, tab, taped):
+    w = inputs.orbits_forward(n=200, seed=54)
+    w = {**w, "tableau": tab, "t_out": None}
+    prob = _problem(w)
+    sol = _solve_taped(prob, k=7) if taped else api.solve(prob)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(14)
+    tq = np.sort(rng.uniform(0.0, 50.0, (9, 200)), axis=0)
+    tq[0] = 0.0
+    tq[-1] = 50.0
+    yq = api.dense_eval(sol, tq).cpu().numpy()
+    o = oracle_solve(orc, {**w, "t_out": tq})
+    err = np.abs(yq - o["y_out"]) / np.maximum(np.abs(o["y_out"]), 1.0)
+    assert err.max() < 1e-9, err.max()
