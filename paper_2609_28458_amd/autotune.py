@@ -1,0 +1,129 @@
+"""Launch-shape autotuner for the ensemble solver.
+
+For a problem class (right-hand side, tableau, log2 of the ensemble size,
+device) it times candidate launch shapes of the forward kernel -- lanes per
+workgroup, persistent-grid size (one or two wavefronts per SIMD, or the full
+occupancy limit), refill granularity of the work queue -- and, for gradient
+runs, the checkpoint interval k of the tape (forward with tape plus adjoint).
+The fastest shape is cached in a JSON file keyed by problem class.  Timing
+uses HIP events on the stream the kernels run on.
+"""
+from __future__ import annotations
+
+import json
+import math
+import os
+
+import torch
+
+from . import api
+
+CACHE = os.environ.get("GS_AUTOTUNE_CACHE",
+                       os.path.join(os.path.expanduser("~"), ".cache", "gradsolve_autotune.json"))
+
+BLOCKS = (64, 128, 256)
+REFILLS = (1, 16, 64)
+CKPT = (8, 32, 128)
+
+
+def _key(prob: api.Problem, kind: str) -> str:
+    dev = torch.cuda.get_device_name(prob.y0.device)
+    return f"{dev}|{kind}|rhs{prob.rhs}|tab{prob.tableau}|n2^{int(math.log2(max(prob.n, 1)))}"
+
+
+def _load():
+    try:
+        with open(CACHE) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def _store(cache):
+    os.makedirs(os.path.dirname(CACHE), exist_ok=True)
+    tmp = CACHE + ".tmp"
+    with open(tmp, "w") as f:
+        json.dump(cache, f, indent=1, sort_keys=True)
+    os.replace(tmp, CACHE)
+
+
+def _time(fn, reps=3):
+    fn()
+    torch.cuda.synchronize()
+    best = float("inf")
+    for _ in range(reps):
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        fn()
+        b.record()
+        torch.cuda.synchronize()
+        best = min(best, a.elapsed_time(b))
+    return best
+
+
+def _grids(prob: api.Problem, block: int):
+    cus = torch.cuda.get_device_properties(prob.y0.device).multi_processor_count
+    waves_per_block = block // 64
+    # one and two wavefronts per SIMD (4 SIMDs per CU), and the occupancy limit
+    return sorted({max(1, (4 * cus) // waves_per_block), max(1, (8 * cus) // waves_per_block), 0})
+
+
+def tune_forward(prob: api.Problem, order=None, base: api.Launch | None = None,
+                 use_cache=True) -> api.Launch:
+    """Fastest forward launch shape for this problem class."""
+    key = _key(prob, "fwd")
+    cache = _load() if use_cache else {}
+    base = base or api.Launch()
+    if key in cache:
+        return api.Launch(**{**base.__dict__, **cache[key]["launch"]})
+    best = None
+    for block in BLOCKS:
+        for grid in _grids(prob, block):
+            for refill in REFILLS:
+                L = api.Launch(**{**base.__dict__, "schedule": "queue", "block": block,
+                                  "grid": grid, "refill": refill})
+                sol = api.Solution(prob, L)
+                if order is not None:
+                    sol.set_order(order)
+                ms = _time(lambda: sol.run())
+                if best is None or ms < best[0]:
+                    best = (ms, {"schedule": "queue", "block": block, "grid": grid,
+                                 "refill": refill})
+    cache[key] = {"ms": best[0], "launch": best[1]}
+    if use_cache:
+        _store(cache)
+    return api.Launch(**{**base.__dict__, **best[1]})
+
+
+def tune_gradient(prob: api.Problem, make_cotangent, base: api.Launch | None = None,
+                  use_cache=True) -> api.Launch:
+    """Fastest checkpoint interval for forward-with-tape plus adjoint.
+
+    ``make_cotangent(sol)`` returns (ybar_final, ybar_out) for a solution.
+    """
+    key = _key(prob, "grad")
+    cache = _load() if use_cache else {}
+    base = base or api.Launch()
+    if key in cache:
+        return api.Launch(**{**base.__dict__, **cache[key]["launch"]})
+    plain = api.solve(prob, base)
+    torch.cuda.synchronize()
+    nmax = int(plain.n_accepted.max())
+    best = None
+    for k in CKPT:
+        L = api.Launch(**{**base.__dict__, "ckpt_every": k, "ckpt_capacity": nmax // k + 2})
+        sol = api.Solution(prob, L)
+
+        def step():
+            sol.run()
+            yf, yo = make_cotangent(sol)
+            api.solve_vjp(sol, ybar_final=yf, ybar_out=yo)
+
+        ms = _time(step)
+        if best is None or ms < best[0]:
+            best = (ms, {"ckpt_every": k, "ckpt_capacity": nmax // k + 2})
+    cache[key] = {"ms": best[0], "launch": best[1]}
+    if use_cache:
+        _store(cache)
+    return api.Launch(**{**base.__dict__, **best[1]})

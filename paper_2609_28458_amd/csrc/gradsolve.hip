@@ -128,6 +128,10 @@ Params make_params(const gs_solve_args* a) {
   P.order = a->order;
   P.refill = a->refill > 0 ? a->refill : 16;
   P.sched_static = a->schedule == GS_SCHED_STATIC ? 1 : 0;
+  P.fast_ctrl = (a->ctrl.beta1 <= 0.0 && a->ctrl.beta2 == 0.0 && a->ctrl.alpha_max <= 100.0 &&
+                 a->ctrl.alpha_min >= 0.01)
+                    ? 1
+                    : 0;
   return P;
 }
 

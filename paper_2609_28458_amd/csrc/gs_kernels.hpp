@@ -88,6 +88,7 @@ struct Params {
   const int64_t* order;
   int32_t refill;
   int32_t sched_static;
+  int32_t fast_ctrl;  // I controller with default exponent and alpha in [0.01, 100]
 };
 
 struct VjpParams {
@@ -143,38 +144,10 @@ __device__ __forceinline__ bool inputs_valid(const Params& P, int64_t i, const I
 
 // Starting step of Hairer, Norsett & Wanner (1993, Sec. II.4); the paper
 // gives none.  RMS norms scaled by atol + rtol |y0|; one extra evaluation.
+// Defined after inv_root; declared here for the kernels.
 template <class TB, class F>
 __device__ double initial_step(const Inputs<F>& in, const double (&y)[F::D],
-                               const double (&f0)[F::D]) {
-  constexpr int D = F::D;
-  const double span = in.t1 - in.t0;
-  double d0 = 0.0, d1 = 0.0;
-#pragma unroll
-  for (int c = 0; c < D; ++c) {
-    const double sc = in.atol + fabs(y[c]) * in.rtol;
-    d0 += (y[c] / sc) * (y[c] / sc);
-    d1 += (f0[c] / sc) * (f0[c] / sc);
-  }
-  d0 = sqrt(d0 / D);
-  d1 = sqrt(d1 / D);
-  double h0 = (d0 < 1e-5 || d1 < 1e-5) ? 1e-6 : 0.01 * d0 / d1;
-  h0 = dmin(h0, span);
-  double y1[D], f1[D];
-#pragma unroll
-  for (int c = 0; c < D; ++c) y1[c] = y[c] + h0 * f0[c];
-  F::f(in.t0 + h0, y1, in.par, f1);
-  double d2 = 0.0;
-#pragma unroll
-  for (int c = 0; c < D; ++c) {
-    const double sc = in.atol + fabs(y[c]) * in.rtol;
-    const double r = (f1[c] - f0[c]) / sc;
-    d2 += r * r;
-  }
-  d2 = sqrt(d2 / D) / h0;
-  const double h1 = (d1 <= 1e-15 && d2 <= 1e-15) ? dmax(1e-6, h0 * 1e-3)
-                                                 : pow(0.01 / dmax(d1, d2), 1.0 / TB::ORDER);
-  return dmin(dmin(100.0 * h0, h1), span);
-}
+                               const double (&f0)[F::D]);
 
 // Stages 2..s of one step of length h from (t, y) with k[0] = f(t, y)
 // given (eq:rk).  Returns y+ in yn.  For FSAL pairs the last stage point is
@@ -217,12 +190,14 @@ __device__ __forceinline__ void rk_stages(const typename F::Par& par, double t, 
   }
 }
 
-// Scaled RMS norm (eq:errnorm) of e = h sum_j (b_j - bhat_j) k_j.
+// Square of the scaled RMS norm of eq:errnorm, for e = h sum_j (b_j -
+// bhat_j) k_j.  The square suffices: accept iff it is <= 1, and the
+// controller takes its power directly, so no square root is needed.
 template <class TB, class F>
-__device__ __forceinline__ double error_norm(double h, const double (&y)[F::D],
-                                             const double (&yn)[F::D],
-                                             const double (&k)[TB::S][F::D], double rtol,
-                                             double atol) {
+__device__ __forceinline__ double error_norm2(double h, const double (&y)[F::D],
+                                              const double (&yn)[F::D],
+                                              const double (&k)[TB::S][F::D], double rtol,
+                                              double atol) {
   constexpr int D = F::D;
   double acc2 = 0.0;
 #pragma unroll
@@ -235,17 +210,78 @@ __device__ __forceinline__ double error_norm(double h, const double (&y)[F::D],
     });
     e *= h;
     const double sc = fma(rtol, dmax(fabs(y[c]), fabs(yn[c])), atol);
-    const double r = e / sc;
+    const double r = e * fast_rcp(sc);
     acc2 = fma(r, r, acc2);
   }
-  return sqrt(acc2 / D);
+  return acc2 * (1.0 / D);
 }
 
-// Value at t + sigma h inside an accepted step: the polynomial of eq:dense,
-// or (Verner 7) a shortened step of length sigma h from (t, y) reusing k[0].
+// x^(-1/M) for x in [1e-30, 1e30]: an FP32 seed from the hardware log2/exp2,
+// then two Newton steps on r^M x = 1 in FP64 (relative error ~(M+1)/2 eps^2
+// per step, so full double precision after two).
+template <int M>
+__device__ __forceinline__ double inv_root(double x) {
+  const float lx = __builtin_amdgcn_logf(static_cast<float>(x));
+  double r = static_cast<double>(__builtin_amdgcn_exp2f(lx * (-1.0f / M)));
+#pragma unroll
+  for (int it = 0; it < 2; ++it) {
+    double rm = r;  // r^M by repeated multiplication
+#pragma unroll
+    for (int q = 1; q < M; ++q) rm *= r;
+    const double u = rm * x;
+    r = fma(r * (1.0 / M), 1.0 - u, r);
+  }
+  return r;
+}
+
+template <class TB, class F>
+__device__ double initial_step(const Inputs<F>& in, const double (&y)[F::D],
+                               const double (&f0)[F::D]) {
+  constexpr int D = F::D;
+  const double span = in.t1 - in.t0;
+  double isc[D];
+  double d0 = 0.0, d1 = 0.0;
+#pragma unroll
+  for (int c = 0; c < D; ++c) {
+    isc[c] = fast_rcp(in.atol + fabs(y[c]) * in.rtol);
+    d0 = fma(y[c] * isc[c], y[c] * isc[c], d0);
+    d1 = fma(f0[c] * isc[c], f0[c] * isc[c], d1);
+  }
+  d0 = sqrt(d0 * (1.0 / D));
+  d1 = sqrt(d1 * (1.0 / D));
+  double h0 = (d0 < 1e-5 || d1 < 1e-5) ? 1e-6 : 0.01 * d0 * fast_rcp(d1);
+  h0 = dmin(h0, span);
+  double y1[D], f1[D];
+#pragma unroll
+  for (int c = 0; c < D; ++c) y1[c] = y[c] + h0 * f0[c];
+  F::f(in.t0 + h0, y1, in.par, f1);
+  double d2 = 0.0;
+#pragma unroll
+  for (int c = 0; c < D; ++c) {
+    const double r = (f1[c] - f0[c]) * isc[c];
+    d2 = fma(r, r, d2);
+  }
+  d2 = sqrt(d2 * (1.0 / D)) * fast_rcp(h0);
+  double h1;
+  if (d1 <= 1e-15 && d2 <= 1e-15) {
+    h1 = dmax(1e-6, h0 * 1e-3);
+  } else {
+    // (0.01 / max(d1, d2))^(1/nu)
+    const double x = dmax(d1, d2) * 100.0;
+    h1 = (x >= 1e-30 && x <= 1e30) ? inv_root<TB::ORDER>(x) : pow(x, -1.0 / TB::ORDER);
+  }
+  return dmin(dmin(100.0 * h0, h1), span);
+}
+
+// Value at t + sigma h inside an accepted step, evaluated once the step is
+// committed.  Polynomial pairs use eq:dense rewritten about the end of the
+// step, y + h sum_j b_j(sigma) k_j = y+ - h sum_j (b_j - b_j(sigma)) k_j, so the
+// start state need not stay live; Verner 7 takes a shortened step of length
+// sigma h from (t, y_start) reusing k[0] = f(t, y_start).
 template <class TB, class F>
 __device__ __forceinline__ void dense_value(const typename F::Par& par, double t, double h,
-                                            double sigma, const double (&y)[F::D],
+                                            double sigma, const double (&y_end)[F::D],
+                                            const double (&y_start)[F::D],
                                             const double (&k)[TB::S][F::D],
                                             double (&out)[F::D]) {
   constexpr int S = TB::S, D = F::D;
@@ -258,30 +294,44 @@ __device__ __forceinline__ void dense_value(const typename F::Par& par, double t
         constexpr int q = decltype(Q)::value;
         acc = fma(acc, sigma, TB::Bs(j, q));
       });
-      w[j] = acc * sigma;
+      w[j] = TB::B(j) - acc * sigma;
     });
 #pragma unroll
     for (int c = 0; c < D; ++c) {
       double acc = 0.0;
 #pragma unroll
       for (int j = 0; j < S; ++j) acc = fma(w[j], k[j][c], acc);
-      out[c] = fma(h, acc, y[c]);
+      out[c] = fma(-h, acc, y_end[c]);
     }
   } else {
     double ks[S][D];
 #pragma unroll
     for (int c = 0; c < D; ++c) ks[0][c] = k[0][c];
-    rk_stages<TB, F>(par, t, sigma * h, y, ks, out);
+    rk_stages<TB, F>(par, t, sigma * h, y_start, ks, out);
   }
 }
 
-// Controller of eq:controller (PI form, beta2 = 0 is the paper's I form).
-__device__ __forceinline__ double step_factor(const Params& P, double b1, double en,
-                                              double err_prev, bool finite) {
-  if (!finite) return P.amin;
-  if (en == 0.0) return P.amax;
-  double raw = P.safety * pow(en, -b1);
-  if (P.beta2 != 0.0) raw *= pow(err_prev, P.beta2);
+// Controller of eq:controller from the squared norm en2 = ||e||^2.  The
+// paper's I form safety * ||e||^(-1/nu) = safety * en2^(-1/(2 nu)) takes the
+// Newton root (P.fast_ctrl, decided once per launch so the branch is
+// uniform).  Clamping en2 to [1e-30, 1e30] changes nothing: outside that
+// range the raw factor lies beyond [alpha_min, alpha_max] whenever
+// alpha_max <= 100 and alpha_min >= 0.01, which fast_ctrl requires.  The PI
+// form (beta2 != 0) or another exponent uses pow.
+template <class TB>
+__device__ __forceinline__ double step_factor(const Params& P, double en2, double err_prev,
+                                              bool finite) {
+  double raw;
+  if (P.fast_ctrl) {
+    const double x = dmin(dmax(en2, 1e-30), 1e30);
+    raw = P.safety * inv_root<2 * TB::ORDER>(x);
+  } else {
+    const double b1 = P.beta1 > 0.0 ? P.beta1 : 1.0 / TB::ORDER;
+    raw = P.safety * pow(en2, -0.5 * b1);
+    if (P.beta2 != 0.0) raw *= pow(err_prev, P.beta2);
+  }
+  raw = (en2 == 0.0) ? P.amax : raw;
+  raw = finite ? raw : P.amin;
   return dmin(P.amax, dmax(P.amin, raw));
 }
 
@@ -308,11 +358,12 @@ struct Attempt {
   double t_start, h_used, t_new;
 };
 
-// One step attempt with everything the controller does after it.  Node
-// output is done by the caller through `on_accept`, which sees the state
-// before the update (t, y, k of the step) together with y+ and t_new.
+// One step attempt with everything the controller does after it.  On
+// acceptance the new state is committed first and `on_accept(s, t_start, h,
+// y_start)` then sees y = y+, t = t_new and the step's stages k (k[0] still
+// f(t_start, y_start)); y_start is only meaningful for shortened-step pairs.
 template <class TB, class F, class OnAccept>
-__device__ __forceinline__ Attempt attempt(const Params& P, Traj<TB, F>& s, double b1,
+__device__ __forceinline__ Attempt attempt(const Params& P, Traj<TB, F>& s,
                                            OnAccept&& on_accept) {
   constexpr int S = TB::S, D = F::D;
   Attempt a;
@@ -329,21 +380,27 @@ __device__ __forceinline__ Attempt attempt(const Params& P, Traj<TB, F>& s, doub
   a.h_used = hh;
   double yn[D];
   rk_stages<TB, F>(s.in.par, s.t, hh, s.y, s.k, yn);
-  const double en = error_norm<TB, F>(hh, s.y, yn, s.k, s.in.rtol, s.in.atol);
-  const bool finite = (en == en) && (en < __builtin_inf());
-  const double factor = step_factor(P, b1, en, s.err_prev, finite);
-  if (finite && en <= 1.0) {
+  const double en2 = error_norm2<TB, F>(hh, s.y, yn, s.k, s.in.rtol, s.in.atol);
+  const bool finite = (en2 == en2) && (en2 < __builtin_inf());
+  const double factor = step_factor<TB>(P, en2, s.err_prev, finite);
+  if (finite && en2 <= 1.0) {
     a.accepted = true;
     a.t_new = last ? s.in.t1 : s.t + hh;
-    on_accept(s, hh, a.t_new, yn);
-    s.t = a.t_new;
+    double ystart[D];
     bool fin = true;
 #pragma unroll
     for (int c = 0; c < D; ++c) {
+      if constexpr (!TB::POLY_DENSE) ystart[c] = s.y[c];
       s.y[c] = yn[c];
       fin = fin && (yn[c] == yn[c]) && (fabs(yn[c]) < __builtin_inf());
     }
-    s.err_prev = dmax(en, 1e-4);
+    s.t = a.t_new;
+    if constexpr (TB::POLY_DENSE) {
+      on_accept(s, a.t_start, hh, s.y);
+    } else {
+      on_accept(s, a.t_start, hh, ystart);
+    }
+    if (P.beta2 != 0.0) s.err_prev = dmax(sqrt(en2), 1e-4);
     ++s.nacc;
     if constexpr (TB::FSAL) {
 #pragma unroll
@@ -429,16 +486,18 @@ __device__ __forceinline__ uint64_t lanemask_lt() {
 // Occupancy target of the forward kernel: the stage array k[S][D] dominates
 // the live registers; up to 63 doubles (126 VGPRs) two waves per SIMD fit in
 // the 512-entry register file without spilling, beyond that one.
+#ifndef GS_FWD_WAVES
+#define GS_FWD_WAVES 2
+#endif
 template <class TB, class F>
 struct FwdOccupancy {
-  static constexpr int waves = (TB::S * F::D > 63) ? 1 : 2;
+  static constexpr int waves = (TB::S * F::D > 63) ? 1 : GS_FWD_WAVES;
 };
 
 template <class TB, class F>
 __global__ void __launch_bounds__(256)
     __attribute__((amdgpu_waves_per_eu(FwdOccupancy<TB, F>::waves, 8))) solve_kernel(Params P) {
   constexpr int D = F::D;
-  const double b1 = P.beta1 > 0.0 ? P.beta1 : 1.0 / TB::ORDER;
   Traj<TB, F> s;
   int64_t idx = -1;
   int32_t kp = 0;
@@ -535,17 +594,16 @@ __global__ void __launch_bounds__(256)
         continue;
       }
       const Attempt a = attempt<TB, F>(
-          P, s, b1,
-          [&](const Traj<TB, F>& st, double hh, double t_new, const double (&yn)[D]) {
+          P, s, [&](const Traj<TB, F>& st, double t_old, double hh, const double (&ys)[D]) {
             while (kp < P.K) {
               const double tq = node_time(P, kp, idx);
-              if (!(tq <= t_new)) break;
+              if (!(tq <= st.t)) break;
               double out[D];
-              if (tq == t_new) {
+              if (tq == st.t) {
 #pragma unroll
-                for (int c = 0; c < D; ++c) out[c] = yn[c];
+                for (int c = 0; c < D; ++c) out[c] = st.y[c];
               } else {
-                dense_value<TB, F>(st.in.par, st.t, hh, (tq - st.t) / hh, st.y, st.k, out);
+                dense_value<TB, F>(st.in.par, t_old, hh, (tq - t_old) / hh, st.y, ys, st.k, out);
               }
 #pragma unroll
               for (int c = 0; c < D; ++c) P.y_out[((int64_t)c * P.K + kp) * P.n + idx] = out[c];
@@ -672,7 +730,6 @@ template <class TB, class F, int R>
 __global__ void __launch_bounds__(256) vjp_kernel(Params P, VjpParams V) {
   constexpr int D = F::D, NP = F::P;
   constexpr int SREC = 2 + D;
-  const double b1 = P.beta1 > 0.0 ? P.beta1 : 1.0 / TB::ORDER;
   const int lane = threadIdx.x & 63;
   const int64_t slot = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   double* scr = V.scratch + slot * (int64_t)P.ckpt_every * SREC;
@@ -717,15 +774,18 @@ __global__ void __launch_bounds__(256) vjp_kernel(Params P, VjpParams V) {
         s.nrej = 0;
         int j = 0;
         while (j < m) {
-          const Attempt a = attempt<TB, F>(
-              P, s, b1, [&](const Traj<TB, F>& sb, double hh, double, const double (&)[D]) {
-                double* rec = scr + (int64_t)j * SREC;
-                rec[0] = sb.t;
-                rec[1] = hh;
+          // Record the start of the attempt in slot j; it is kept if the
+          // attempt is accepted.
+          double* rec = scr + (int64_t)j * SREC;
+          rec[0] = s.t;
 #pragma unroll
-                for (int c = 0; c < D; ++c) rec[2 + c] = sb.y[c];
-              });
-          if (a.accepted) ++j;
+          for (int c = 0; c < D; ++c) rec[2 + c] = s.y[c];
+          const Attempt a = attempt<TB, F>(
+              P, s, [&](const Traj<TB, F>&, double, double, const double (&)[D]) {});
+          if (a.accepted) {
+            rec[1] = a.h_used;
+            ++j;
+          }
           if (a.finished && j < m) break;  // cannot happen on a faithful replay
         }
         if (j < m) {
@@ -858,7 +918,6 @@ template <class TB, class F>
 __global__ void __launch_bounds__(256) dense_kernel(Params P, int32_t Q, const double* tq_all,
                                                     double* yq_all) {
   constexpr int D = F::D;
-  const double b1 = P.beta1 > 0.0 ? P.beta1 : 1.0 / TB::ORDER;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= P.n) return;
   Traj<TB, F> s;
@@ -906,14 +965,13 @@ __global__ void __launch_bounds__(256) dense_kernel(Params P, int32_t Q, const d
       s.nrej = 0;
       for (int guard = 0; guard < 100000000 && !done; ++guard) {
         const Attempt a = attempt<TB, F>(
-            P, s, b1,
-            [&](const Traj<TB, F>& sb, double hh, double t_new, const double (&yn)[D]) {
-              if (tq <= t_new) {
-                if (tq == t_new) {
+            P, s, [&](const Traj<TB, F>& sb, double t_old, double hh, const double (&ys)[D]) {
+              if (tq <= sb.t) {
+                if (tq == sb.t) {
 #pragma unroll
-                  for (int c = 0; c < D; ++c) out[c] = yn[c];
+                  for (int c = 0; c < D; ++c) out[c] = sb.y[c];
                 } else {
-                  dense_value<TB, F>(sb.in.par, sb.t, hh, (tq - sb.t) / hh, sb.y, sb.k, out);
+                  dense_value<TB, F>(sb.in.par, t_old, hh, (tq - t_old) / hh, sb.y, ys, sb.k, out);
                 }
                 done = true;
               }

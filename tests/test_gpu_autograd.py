@@ -1,0 +1,77 @@
+"""torch.autograd wrapper (shared-parameter reduction, eq:chain) and the
+launch autotuner, on the GPU."""
+import os
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from gpu_util import oracle_solve  # noqa: E402
+from paper_2609_28458_amd import api, autotune, inputs  # noqa: E402
+from paper_2609_28458_amd.autograd import SolveSpec, solve_ad  # noqa: E402
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a GPU")
+    api.lib()
+
+
+def test_autograd_matches_oracle_sensitivities(orc):
+    w = inputs.orbits_forward(n=300, seed=61)
+    T = torch.as_tensor(np.random.default_rng(2).normal(size=(3, 300)), device="cuda")
+    y0 = torch.as_tensor(w["y0"], device="cuda").requires_grad_(True)
+    th = torch.as_tensor(w["theta"], device="cuda").requires_grad_(True)
+    spec = SolveSpec(w["rhs"], w["tableau"], 0.0, 50.0, 1e-8, 1e-10, w["t_out"], ckpt_every=16)
+    y_out, y_final, status = solve_ad(spec, y0, th)
+    assert bool((status == 0).all())
+    loss = ((y_final[:3] - T) ** 2).sum() + 0.1 * (y_out[3:] ** 2).sum()
+    loss.backward()
+    # The same cotangents through the oracle's forward sensitivities.
+    o = oracle_solve(orc, w, sens_cols=list(range(9)))
+    ybf = np.zeros((6, 300))
+    ybf[:3] = 2.0 * (o["y_final"][:3] - T.cpu().numpy())
+    ybo = np.zeros((6, 64, 300))
+    ybo[3:] = 0.2 * o["y_out"][3:]
+    g = np.einsum("jn,jcn->cn", ybf, o["S_final"]) + np.einsum("jkn,jckn->cn", ybo, o["S_out"])
+    gy = y0.grad.cpu().numpy()
+    np.testing.assert_allclose(gy, g[:6], rtol=0, atol=1e-8 * np.abs(g[:6]).max())
+    # shared theta: the cotangents of all trajectories are summed (eq:chain)
+    gt = th.grad.cpu().numpy()
+    ref = g[6:].sum(axis=1)
+    np.testing.assert_allclose(gt, ref, rtol=1e-9, atol=0)
+
+
+def test_tape_capacity_grows_to_fit():
+    w = inputs.orbits_gradient(n=128, seed=62)
+    y0 = torch.as_tensor(w["y0"], device="cuda").requires_grad_(True)
+    th = torch.as_tensor(w["theta"], device="cuda").requires_grad_(True)
+    spec = SolveSpec(w["rhs"], w["tableau"], 0.0, 100.0, 1e-8, 1e-10, None, ckpt_every=4)
+    _, y_final, status = solve_ad(spec, y0, th)
+    assert bool((status == 0).all())  # the first tape (64 checkpoints) was too small
+    assert spec.last_solution.launch.ckpt_capacity * 4 >= int(spec.last_solution.n_accepted.max())
+    y_final[:3].sum().backward()
+    assert torch.isfinite(y0.grad).all() and torch.isfinite(th.grad).all()
+
+
+def test_autotuned_launch_gives_identical_results(tmp_path, monkeypatch):
+    monkeypatch.setattr(autotune, "CACHE", str(tmp_path / "tune.json"))
+    w = inputs.orbits_uneven(n=4096, seed=63)
+    prob = api.make_problem(w["rhs"], w["tableau"], w["y0"], w["theta"], w["t0"], w["t1"],
+                            w["rtol"], w["atol"])
+    L = autotune.tune_forward(prob)
+    assert os.path.exists(autotune.CACHE)
+    assert autotune.tune_forward(prob).__dict__ == L.__dict__  # served from the cache
+    a = api.solve(prob, L)
+    b = api.solve(prob, api.Launch(schedule="static"))
+    torch.cuda.synchronize()
+    assert torch.equal(a.y_final, b.y_final) and torch.equal(a.n_accepted, b.n_accepted)
+
+    def cot(sol):
+        return torch.ones((1, 6, prob.n), dtype=torch.float64, device="cuda"), None
+
+    G = autotune.tune_gradient(prob, cot)
+    assert G.ckpt_every in autotune.CKPT
