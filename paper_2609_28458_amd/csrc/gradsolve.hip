@@ -158,7 +158,18 @@ struct Ops {
 
 template <class TB, class F>
 void launch_solve(const Params& P, int grid, int block, hipStream_t s) {
-  hipLaunchKernelGGL((gs::solve_kernel<TB, F>), dim3(grid), dim3(block), 0, s, P);
+  if (P.K > 0) {
+    if (P.ckpt_every > 0)
+      hipLaunchKernelGGL((gs::solve_kernel<TB, F, true, true>), dim3(grid), dim3(block), 0, s, P);
+    else
+      hipLaunchKernelGGL((gs::solve_kernel<TB, F, true, false>), dim3(grid), dim3(block), 0, s, P);
+  } else {
+    if (P.ckpt_every > 0)
+      hipLaunchKernelGGL((gs::solve_kernel<TB, F, false, true>), dim3(grid), dim3(block), 0, s, P);
+    else
+      hipLaunchKernelGGL((gs::solve_kernel<TB, F, false, false>), dim3(grid), dim3(block), 0, s,
+                         P);
+  }
 }
 template <class TB, class F>
 void launch_vjp(const Params& P, const VjpParams& V, int grid, int block, hipStream_t s) {
@@ -174,7 +185,8 @@ void launch_dense(const Params& P, int32_t Q, const double* tq, double* yq, int 
 }
 template <class TB, class F>
 Ops make_ops() {
-  return Ops{reinterpret_cast<const void*>(&gs::solve_kernel<TB, F>), &launch_solve<TB, F>,
+  return Ops{reinterpret_cast<const void*>(&gs::solve_kernel<TB, F, true, true>),
+             &launch_solve<TB, F>,
              &launch_vjp<TB, F>, &launch_dense<TB, F>};
 }
 template <class F>

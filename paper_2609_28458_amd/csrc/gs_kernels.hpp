@@ -199,7 +199,7 @@ __device__ __forceinline__ double error_norm2(double h, const double (&y)[F::D],
                                               const double (&k)[TB::S][F::D], double rtol,
                                               double atol) {
   constexpr int D = F::D;
-  double acc2 = 0.0;
+  double sq[D];
 #pragma unroll
   for (int c = 0; c < D; ++c) {
     double e = 0.0;
@@ -210,10 +210,29 @@ __device__ __forceinline__ double error_norm2(double h, const double (&y)[F::D],
     });
     e *= h;
     const double sc = fma(rtol, dmax(fabs(y[c]), fabs(yn[c])), atol);
-    const double r = e * fast_rcp(sc);
-    acc2 = fma(r, r, acc2);
+    const double r = e * fast_rcp1(sc);
+    sq[c] = r * r;
   }
-  return acc2 * (1.0 / D);
+  // pairwise sum: a shorter dependency chain at the end of the attempt
+#pragma unroll
+  for (int w = 1; w < D; w *= 2) {
+#pragma unroll
+    for (int c = 0; c + w < D; c += 2 * w) sq[c] += sq[c + w];
+  }
+  return sq[0] * (1.0 / D);
+}
+
+// r^M by repeated squaring (M a compile-time constant).
+template <int M>
+__device__ __forceinline__ double ipow(double r) {
+  if constexpr (M == 1) {
+    return r;
+  } else if constexpr (M % 2 == 0) {
+    const double h = ipow<M / 2>(r);
+    return h * h;
+  } else {
+    return ipow<M - 1>(r) * r;
+  }
 }
 
 // x^(-1/M) for x in [1e-30, 1e30]: an FP32 seed from the hardware log2/exp2,
@@ -225,10 +244,7 @@ __device__ __forceinline__ double inv_root(double x) {
   double r = static_cast<double>(__builtin_amdgcn_exp2f(lx * (-1.0f / M)));
 #pragma unroll
   for (int it = 0; it < 2; ++it) {
-    double rm = r;  // r^M by repeated multiplication
-#pragma unroll
-    for (int q = 1; q < M; ++q) rm *= r;
-    const double u = rm * x;
+    const double u = ipow<M>(r) * x;
     r = fma(r * (1.0 / M), 1.0 - u, r);
   }
   return r;
@@ -317,9 +333,11 @@ __device__ __forceinline__ void dense_value(const typename F::Par& par, double t
 // uniform).  Clamping en2 to [1e-30, 1e30] changes nothing: outside that
 // range the raw factor lies beyond [alpha_min, alpha_max] whenever
 // alpha_max <= 100 and alpha_min >= 0.01, which fast_ctrl requires.  The PI
-// form (beta2 != 0) or another exponent uses pow.
+// form (beta2 != 0) or another exponent uses pow; the previous norm is kept
+// squared (err_prev2 = max(||e_prev||^2, 1e-8), i.e. ||e_prev|| floored at
+// 1e-4) so no square root is taken on the hot path.
 template <class TB>
-__device__ __forceinline__ double step_factor(const Params& P, double en2, double err_prev,
+__device__ __forceinline__ double step_factor(const Params& P, double en2, double err_prev2,
                                               bool finite) {
   double raw;
   if (P.fast_ctrl) {
@@ -328,7 +346,7 @@ __device__ __forceinline__ double step_factor(const Params& P, double en2, doubl
   } else {
     const double b1 = P.beta1 > 0.0 ? P.beta1 : 1.0 / TB::ORDER;
     raw = P.safety * pow(en2, -0.5 * b1);
-    if (P.beta2 != 0.0) raw *= pow(err_prev, P.beta2);
+    if (P.beta2 != 0.0) raw *= pow(err_prev2, 0.5 * P.beta2);
   }
   raw = (en2 == 0.0) ? P.amax : raw;
   raw = finite ? raw : P.amin;
@@ -346,8 +364,10 @@ struct Traj {
   Inputs<F> in;
   double y[D];
   double k[S][D];
-  double t, h, err_prev;
+  double t, h;
+  double err_prev2;  // squared norm of the last accepted step (PI control)
   int32_t nacc, nrej, nanrun;
+  int32_t ck_left;   // accepted steps until the next checkpoint
 };
 
 // Outcome of one attempt.
@@ -358,18 +378,17 @@ struct Attempt {
   double t_start, h_used, t_new;
 };
 
-// One step attempt with everything the controller does after it.  On
-// acceptance the new state is committed first and `on_accept(s, t_start, h,
-// y_start)` then sees y = y+, t = t_new and the step's stages k (k[0] still
-// f(t_start, y_start)); y_start is only meaningful for shortened-step pairs.
+// One step attempt with everything the controller does after it.  The
+// accept/reject update is written as per-lane selects (no divergent
+// branch around the state); only output nodes run under a branch:
+// `on_accept(s, t_start, h, y_start)` sees y = y+, t = t_new and the step's
+// stages k (k[0] still f(t_start, y_start)); y_start is only meaningful for
+// shortened-step pairs.
 template <class TB, class F, class OnAccept>
 __device__ __forceinline__ Attempt attempt(const Params& P, Traj<TB, F>& s,
                                            OnAccept&& on_accept) {
   constexpr int S = TB::S, D = F::D;
   Attempt a;
-  a.accepted = false;
-  a.finished = false;
-  a.status = ST_OK;
   a.t_start = s.t;
   bool last = false;
   double hh = s.h;
@@ -381,60 +400,48 @@ __device__ __forceinline__ Attempt attempt(const Params& P, Traj<TB, F>& s,
   double yn[D];
   rk_stages<TB, F>(s.in.par, s.t, hh, s.y, s.k, yn);
   const double en2 = error_norm2<TB, F>(hh, s.y, yn, s.k, s.in.rtol, s.in.atol);
-  const bool finite = (en2 == en2) && (en2 < __builtin_inf());
-  const double factor = step_factor<TB>(P, en2, s.err_prev, finite);
-  if (finite && en2 <= 1.0) {
-    a.accepted = true;
-    a.t_new = last ? s.in.t1 : s.t + hh;
-    double ystart[D];
-    bool fin = true;
+  // x - x == 0 exactly when x is finite; no short-circuit branches.
+  const bool finite = (en2 - en2) == 0.0;
+  const double factor = step_factor<TB>(P, en2, s.err_prev2, finite);
+  const bool acc = finite & (en2 <= 1.0);
+  a.accepted = acc;
+  const double t_new = last ? s.in.t1 : s.t + hh;
+  a.t_new = t_new;
+  double ystart[D];
+  double probe = 0.0;  // becomes NaN if any component of y+ is not finite
 #pragma unroll
-    for (int c = 0; c < D; ++c) {
-      if constexpr (!TB::POLY_DENSE) ystart[c] = s.y[c];
-      s.y[c] = yn[c];
-      fin = fin && (yn[c] == yn[c]) && (fabs(yn[c]) < __builtin_inf());
-    }
-    s.t = a.t_new;
+  for (int c = 0; c < D; ++c) {
+    if constexpr (!TB::POLY_DENSE) ystart[c] = s.y[c];
+    probe = fma(yn[c], 0.0, probe);
+    s.y[c] = acc ? yn[c] : s.y[c];
+  }
+  const bool fin = probe == 0.0;
+  s.t = acc ? t_new : s.t;
+  if (acc) {
     if constexpr (TB::POLY_DENSE) {
       on_accept(s, a.t_start, hh, s.y);
     } else {
       on_accept(s, a.t_start, hh, ystart);
     }
-    if (P.beta2 != 0.0) s.err_prev = dmax(sqrt(en2), 1e-4);
-    ++s.nacc;
-    if constexpr (TB::FSAL) {
+  }
+  if constexpr (TB::FSAL) {
 #pragma unroll
-      for (int c = 0; c < D; ++c) s.k[0][c] = s.k[S - 1][c];
-    } else {
-      F::f(s.t, s.y, s.in.par, s.k[0]);
-    }
-    s.nanrun = 0;
-    if (!fin) {
-      a.finished = true;
-      a.status = ST_NONFINITE;
-      return a;
-    }
-    if (last) {
-      a.finished = true;
-      return a;
-    }
+    for (int c = 0; c < D; ++c) s.k[0][c] = acc ? s.k[S - 1][c] : s.k[0][c];
   } else {
-    ++s.nrej;
-    if (!finite) {
-      if (++s.nanrun >= 50) {
-        a.finished = true;
-        a.status = ST_NONFINITE;
-        return a;
-      }
-    } else {
-      s.nanrun = 0;
-    }
+    // A rejected lane recomputes f at its unchanged (t, y): the same value.
+    F::f(s.t, s.y, s.in.par, s.k[0]);
   }
+  s.err_prev2 = acc ? dmax(en2, 1e-8) : s.err_prev2;
+  s.nacc += acc ? 1 : 0;
+  s.nrej += acc ? 0 : 1;
+  s.nanrun = finite ? 0 : s.nanrun + 1;
   s.h = hh * factor;
-  if (underflow(s.h, s.t)) {
-    a.finished = true;
-    a.status = ST_DT_UNDERFLOW;
-  }
+  const bool bad_state = acc & !fin;
+  const bool nan_fail = !finite & (s.nanrun >= 50);
+  const bool done = acc & last;
+  const bool tiny = !done & underflow(s.h, s.t);
+  a.finished = bad_state | nan_fail | done | tiny;
+  a.status = (bad_state | nan_fail) ? ST_NONFINITE : (tiny ? ST_DT_UNDERFLOW : ST_OK);
   return a;
 }
 
@@ -450,7 +457,7 @@ __device__ __forceinline__ void write_checkpoint(const Params& P, int64_t i, int
   double* r = tape_record<TB, F>(P, i, c);
   r[0] = s.t;
   r[1] = s.h;
-  r[2] = s.err_prev;
+  r[2] = s.err_prev2;
 #pragma unroll
   for (int j = 0; j < F::D; ++j) {
     r[3 + j] = s.y[j];
@@ -464,7 +471,7 @@ __device__ __forceinline__ void read_checkpoint(const Params& P, int64_t i, int 
   const double* r = tape_record<TB, F>(P, i, c);
   s.t = r[0];
   s.h = r[1];
-  s.err_prev = r[2];
+  s.err_prev2 = r[2];
 #pragma unroll
   for (int j = 0; j < F::D; ++j) {
     s.y[j] = r[3 + j];
@@ -494,7 +501,10 @@ struct FwdOccupancy {
   static constexpr int waves = (TB::S * F::D > 63) ? 1 : GS_FWD_WAVES;
 };
 
-template <class TB, class F>
+// NODES: the call has output nodes (K > 0); TAPE: it keeps a checkpoint
+// tape.  The host picks the variant, so a plain solve runs a loop with
+// neither check in it.
+template <class TB, class F, bool NODES, bool TAPE>
 __global__ void __launch_bounds__(256)
     __attribute__((amdgpu_waves_per_eu(FwdOccupancy<TB, F>::waves, 8))) solve_kernel(Params P) {
   constexpr int D = F::D;
@@ -507,7 +517,7 @@ __global__ void __launch_bounds__(256)
 
   // Write the final results of the lane's trajectory and free the lane.
   auto finish = [&](int32_t st) {
-    for (; kp < P.K; ++kp) {
+    for (; NODES && kp < P.K; ++kp) {
 #pragma unroll
       for (int c = 0; c < D; ++c)
         P.y_out[((int64_t)c * P.K + kp) * P.n + idx] = __builtin_nan("");
@@ -527,7 +537,7 @@ __global__ void __launch_bounds__(256)
     kp = 0;
     overflow = false;
     s.nacc = s.nrej = s.nanrun = 0;
-    s.err_prev = 1.0;
+    s.err_prev2 = 1.0;
     load_inputs<F>(P, i, s.in, s.y);
     s.t = s.in.t0;
     bool fin = true;
@@ -538,7 +548,7 @@ __global__ void __launch_bounds__(256)
       return;
     }
     // Nodes at t0 take y0.
-    while (kp < P.K && node_time(P, kp, i) <= s.in.t0) {
+    while (NODES && kp < P.K && node_time(P, kp, i) <= s.in.t0) {
 #pragma unroll
       for (int c = 0; c < D; ++c) P.y_out[((int64_t)c * P.K + kp) * P.n + i] = s.y[c];
       ++kp;
@@ -553,7 +563,8 @@ __global__ void __launch_bounds__(256)
     }
     F::f(s.t, s.y, s.in.par, s.k[0]);
     s.h = P.h0 > 0.0 ? dmin(P.h0, s.in.t1 - s.in.t0) : initial_step<TB, F>(s.in, s.y, s.k[0]);
-    if (P.ckpt_every > 0) {
+    s.ck_left = P.ckpt_every;
+    if (TAPE) {
       if (P.ckpt_cap > 0)
         write_checkpoint<TB, F>(P, i, 0, s);
       else
@@ -566,6 +577,9 @@ __global__ void __launch_bounds__(256)
     if (g < P.n) start(g);
   }
 
+  // Outer loop: bookkeeping (retire, refill).  Inner loop: step attempts of
+  // the live lanes until one of them finishes, so the hot loop holds only
+  // the attempt and the rare output and checkpoint writes.
   for (;;) {
     if (!queue_empty) {
       const uint64_t idle = __ballot(!live);
@@ -588,38 +602,50 @@ __global__ void __launch_bounds__(256)
       if (queue_empty) break;
       continue;
     }
-    if (live) {
-      if ((int64_t)s.nacc + s.nrej >= P.max_steps) {
-        finish(ST_MAX_STEPS);
-        continue;
-      }
-      const Attempt a = attempt<TB, F>(
-          P, s, [&](const Traj<TB, F>& st, double t_old, double hh, const double (&ys)[D]) {
-            while (kp < P.K) {
-              const double tq = node_time(P, kp, idx);
-              if (!(tq <= st.t)) break;
-              double out[D];
-              if (tq == st.t) {
+    int32_t st = -1;  // status once this lane's trajectory has finished
+    for (;;) {
+      if (live) {
+        if ((int64_t)s.nacc + s.nrej >= P.max_steps) {
+          st = ST_MAX_STEPS;
+        } else {
+          const Attempt a = attempt<TB, F>(
+              P, s, [&](const Traj<TB, F>& sa, double t_old, double hh, const double (&ys)[D]) {
+                if constexpr (!NODES) return;
+                while (kp < P.K) {
+                  const double tq = node_time(P, kp, idx);
+                  if (!(tq <= sa.t)) break;
+                  double out[D];
+                  if (tq == sa.t) {
 #pragma unroll
-                for (int c = 0; c < D; ++c) out[c] = st.y[c];
-              } else {
-                dense_value<TB, F>(st.in.par, t_old, hh, (tq - t_old) / hh, st.y, ys, st.k, out);
-              }
+                    for (int c = 0; c < D; ++c) out[c] = sa.y[c];
+                  } else {
+                    dense_value<TB, F>(sa.in.par, t_old, hh, (tq - t_old) / hh, sa.y, ys, sa.k,
+                                       out);
+                  }
 #pragma unroll
-              for (int c = 0; c < D; ++c) P.y_out[((int64_t)c * P.K + kp) * P.n + idx] = out[c];
-              ++kp;
+                  for (int c = 0; c < D; ++c)
+                    P.y_out[((int64_t)c * P.K + kp) * P.n + idx] = out[c];
+                  ++kp;
+                }
+              });
+          if (a.finished) {
+            st = a.status;
+          } else if (TAPE) {
+            s.ck_left -= a.accepted ? 1 : 0;
+            if (s.ck_left == 0) {
+              s.ck_left = P.ckpt_every;
+              const int c = s.nacc / P.ckpt_every;
+              if (c < P.ckpt_cap)
+                write_checkpoint<TB, F>(P, idx, c, s);
+              else
+                overflow = true;
             }
-          });
-      if (a.finished) {
-        finish(a.status);
-      } else if (a.accepted && P.ckpt_every > 0 && (s.nacc % P.ckpt_every) == 0) {
-        const int c = s.nacc / P.ckpt_every;
-        if (c < P.ckpt_cap)
-          write_checkpoint<TB, F>(P, idx, c, s);
-        else
-          overflow = true;
+          }
+        }
       }
+      if (__ballot(live && st >= 0) != 0) break;
     }
+    if (live && st >= 0) finish(st);
   }
 }
 
@@ -956,7 +982,7 @@ __global__ void __launch_bounds__(256) dense_kernel(Params P, int32_t Q, const d
 #pragma unroll
         for (int c = 0; c < D; ++c) s.y[c] = y0[c];
         s.t = s.in.t0;
-        s.err_prev = 1.0;
+        s.err_prev2 = 1.0;
         s.nanrun = 0;
         F::f(s.t, s.y, s.in.par, s.k[0]);
         s.h = P.h0 > 0.0 ? dmin(P.h0, s.in.t1 - s.in.t0) : initial_step<TB, F>(s.in, s.y, s.k[0]);

@@ -26,6 +26,13 @@ __device__ __forceinline__ double fast_rcp(double x) {
   return fma(r, e, r);
 }
 
+// 1/x with one Newton step (relative error ~2e-15): for the scales of the
+// error norm, which only decide acceptance.
+__device__ __forceinline__ double fast_rcp1(double x) {
+  const double r = __builtin_amdgcn_rcp(x);
+  return fma(r, fma(-x, r, 1.0), r);
+}
+
 // ---------------------------------------------------------------------------
 // Harmonic oscillator: x' = v, v' = -omega^2 x.  Closed-form test system.
 struct Harmonic {
