@@ -5,25 +5,35 @@ flattened logarithmic halo with per-orbit (v0, q, rc), t_end ~ logU[10, 500]
 and rtol ~ logU[1e-9, 1e-6] (atol = rtol), Tsit5, final states.  One step is
 one complete ensemble solve from device-resident inputs: the work-queue
 reset and the persistent solve kernel, captured once in a hipGraph and
-replayed.  `value` is solves per second.
+replayed; the launch shape comes from the autotuner.  `value` is solves per
+second.
 
 Also reported on the same line:
   * accepted RK steps/s and step attempts/s of the headline run;
-  * the two other launch arms of the same batch (static one lane per
-    trajectory, and one launch per cost bucket);
+  * roofline of the solve kernel: algorithmic FP64 flops per launch over its
+    duration (HIP events on the launch stream) against the FP64 vector peak,
+    HBM traffic from the committed PMC summary when it matches the kernel
+    source, and the critical-path bound of this batch (its longest orbit's
+    attempts times the measured time of one attempt of a lone wavefront);
+  * the same kernel at full occupancy (10^6 uniform orbits) for comparison;
+  * the two other launch arms of the batch (static one lane per trajectory,
+    one launch per cost bucket);
   * the grad/forward time ratio on the gradient workload (100,000 orbits to
     t = 100, Dopri5 1e-8/1e-10, loss sum |x - T|^2): forward with tape plus
     adjoint, over the forward without tape;
-  * roofline: algorithmic FP64 flops of the solve kernel per launch over its
-    measured duration, against the FP64 vector peak (the path is FP64 ALU
-    bound, not MFMA or HBM);
   * cpu_baseline: the CPU oracle on a bounded sample of the same batch.
+
+Modes: `--mode profile` runs the headline steps only (for rocprofv3 kernel
+traces); `--mode traffic` runs one device copy of known size and one headline
+solve (for rocprofv3 FETCH_SIZE / WRITE_SIZE passes).
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -34,16 +44,27 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 PEAK_FP64_VECTOR_TFLOPS = 78.6   # MI355X: 256 CU x 2.4 GHz x 128 FP64 flop/clk
-# Algorithmic FP64 flops of one step attempt (fma = 2, div / sqrt / pow = 1),
-# counted from the kernel's operations:
+# Algorithmic FP64 flops of one step attempt (fma = 2, div / sqrt / root = 1):
 #   Tsit5 stage sums 2 * 6 * (21 + 6) = 324, stage times 12, error weights
 #   2 * 6 * 7 + 6 = 90, norm 6 * 5 + 2 = 32, controller and clipping 5;
 #   log-halo right-hand side 13 per evaluation, 6 evaluations = 78.
 FLOPS_PER_ATTEMPT = {("tsit5", "loghalo"): 541, ("dopri5", "loghalo"): 535}
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles",
+                               "traffic_solve_kernel_tsit5_loghalo_orbits_uneven_100k.md")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2609_28458_amd", "csrc", f)
+                  for f in ("gs_kernels.hpp", "gs_rhs.hpp", "gs_tableaux.hpp")]
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_sha():
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 
 
 def parse():
@@ -52,6 +73,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=100_000)
+    ap.add_argument("--mode", choices=("full", "profile", "traffic"), default="full")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-grad", action="store_true", help="skip the gradient ratio")
     ap.add_argument("--no-arms", action="store_true", help="skip the static and bucket arms")
@@ -72,7 +94,7 @@ def timed(fn, steps, warmup, torch):
     return start.elapsed_time(stop) / steps  # ms per step
 
 
-def cpu_baseline(w, target_s=12.0):
+def cpu_baseline(w, target_thread_seconds=15.0):
     """The oracle as it is, on this host's cores, on a bounded seeded sample."""
     import oracle
 
@@ -87,37 +109,74 @@ def cpu_baseline(w, target_s=12.0):
                          w["t1"][idx], w["rtol"][idx], w["atol"][idx], nthreads=threads)
         return time.perf_counter() - t, o
 
-    m = 400
+    m = 2000
     dt, _ = run(m)
-    m = int(min(n, max(400, m * target_s / max(dt, 1e-3))))
+    m = int(min(n, max(m, m * target_thread_seconds / threads / max(dt, 1e-3))))
     dt, o = run(m)
     return {"value": m / dt, "unit": "solves/s", "cores": threads, "kind": "oracle",
-            "sample": f"{m} seeded orbits of the same 100,000-orbit batch, "
-                      f"{int(o['n_accepted'].sum())} accepted steps, {dt:.1f} s wall"}
+            "sample": f"{m} seeded orbits of the 100,000-orbit uneven batch "
+                      f"({int(o['n_accepted'].sum())} accepted steps), {dt:.2f} s wall on "
+                      f"{threads} threads"}
+
+
+def committed_traffic():
+    """HBM bytes per launch from the committed PMC summary, if it was taken
+    on the current kernel source; else None."""
+    try:
+        text = open(TRAFFIC_SUMMARY).read()
+    except OSError:
+        return None, "no PMC summary"
+    m = re.search(r"kernel source sha: (\w+)", text)
+    b = re.search(r"HBM bytes per launch: ([0-9.eE+]+)", text)
+    if not m or not b:
+        return None, "summary unreadable"
+    if m.group(1) != kernel_source_sha():
+        return None, "kernel changed since the counters were taken"
+    return float(b.group(1)), "committed rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated"
+
+
+def headline(args, torch, api, inputs, autotune):
+    w = inputs.orbits_uneven(n=args.n)
+    prob = api.make_problem(w["rhs"], w["tableau"], w["y0"], w["theta"], w["t0"], w["t1"],
+                            w["rtol"], w["atol"])
+    order = np.argsort(-inputs.predicted_cost(w), kind="stable")
+    return w, prob, order
 
 
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} is not supported "
-              "(the ensemble shards trivially, but this build measures one device).",
-              file=sys.stderr)
+        print(f"bench.py measures exactly one GPU; --gpus {args.gpus} is not supported "
+              "(trajectories are independent; a multi-GPU run would split them by index).", file=sys.stderr)
         sys.exit(2)
     import torch
 
-    from paper_2609_28458_amd import api, inputs
+    from paper_2609_28458_amd import api, autotune, inputs
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     api.lib()
     dev_name = torch.cuda.get_device_name(0)
+    w, prob, order = headline(args, torch, api, inputs, autotune)
+    n = prob.n
 
-    # ---- headline: persistent queue in a hipGraph, longest-first order --------------------
-    w = inputs.orbits_uneven(n=args.n)
-    n = w["y0"].shape[1]
-    prob = api.make_problem(w["rhs"], w["tableau"], w["y0"], w["theta"], w["t0"], w["t1"],
-                            w["rtol"], w["atol"])
-    order = np.argsort(-inputs.predicted_cost(w), kind="stable")
-    launch = api.Launch(schedule="queue", block=256, refill=16)
+    if args.mode == "traffic":
+        # A device copy of exactly 1 GiB calibrates FETCH_SIZE / WRITE_SIZE.
+        a = torch.empty(1 << 27, dtype=torch.float64, device="cuda").fill_(1.0)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        sol = api.Solution(prob, api.Launch(block=256))
+        sol.set_order(order)
+        sol.run()
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": a.numel() * 8, "kernel_source_sha": kernel_source_sha()}))
+        return
+
+    # ---- headline: autotuned persistent queue in a hipGraph, longest-first order -----------
+    if args.mode == "full":
+        launch = autotune.tune_forward(prob, order=order, use_cache=False)
+    else:
+        launch = api.Launch(schedule="queue", block=256, refill=16)
     sol = api.Solution(prob, launch)
     sol.set_order(order)
     graph = api.Graph(sol)
@@ -128,10 +187,13 @@ def main():
     max_att = int((sol.n_accepted + sol.n_rejected).max())
     ok = bool((sol.status == 0).all())
     log(f"[bench] {dev_name}: uneven batch n={n}: {ms:.3f} ms/solve, {attempts} attempts, "
-        f"max per orbit {max_att}, all ok={ok}")
+        f"max per orbit {max_att}, all ok={ok}, launch {launch.__dict__}")
+    if args.mode == "profile":
+        graph.close()
+        return
 
-    # Kernel-only duration with HIP events on the launch stream (the graph's
-    # first node is a one-thread counter reset; the solve kernel dominates).
+    # Kernel duration with HIP events on the launch stream (direct launches:
+    # a one-thread counter reset and the solve kernel).
     s = torch.cuda.current_stream()
 
     def direct():
@@ -139,15 +201,49 @@ def main():
         api.gs_solve(sol.args)
 
     ms_kernel = timed(direct, args.steps, 1, torch)
-    flops = attempts * FLOPS_PER_ATTEMPT[("tsit5", "loghalo")]
-    achieved = flops / (ms_kernel * 1e-3) / 1e12
+    fpa = FLOPS_PER_ATTEMPT[("tsit5", "loghalo")]
+    achieved = attempts * fpa / (ms_kernel * 1e-3) / 1e12
+
+    # One wavefront alone: the time of one attempt on the critical path.
+    lw = dict(w)
+    lw.update(y0=w["y0"][:, :64], theta=w["theta"][:, :64], t1=np.full(64, 300.0),
+              rtol=np.full(64, 1e-9), atol=np.full(64, 1e-9))
+    lprob = api.make_problem(lw["rhs"], lw["tableau"], lw["y0"], lw["theta"], 0.0, lw["t1"],
+                             lw["rtol"], lw["atol"])
+    lsol = api.Solution(lprob, api.Launch(block=64))
+    ms_lone = timed(lambda: lsol.run(), 3, 1, torch)
+    us_per_attempt = ms_lone * 1e3 / int((lsol.n_accepted + lsol.n_rejected).max())
+    bound_ms = max_att * us_per_attempt * 1e-3
+
+    traffic, traffic_src = committed_traffic()
     roofline = {"bound": "alu", "achieved": round(achieved, 3),
                 "peak": PEAK_FP64_VECTOR_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(achieved / PEAK_FP64_VECTOR_TFLOPS, 4), "traffic": None,
-                "kernel": "gs::solve_kernel<Tsit5, LogHalo>",
-                "flops_per_attempt": FLOPS_PER_ATTEMPT[("tsit5", "loghalo")],
-                "attempts_per_launch": attempts, "ms_per_launch": round(ms_kernel, 4)}
-    # Critical path: the longest trajectory alone, at one attempt per lane-step.
+                "frac": round(achieved / PEAK_FP64_VECTOR_TFLOPS, 4), "traffic": traffic,
+                "traffic_source": traffic_src,
+                "kernel": "gs::solve_kernel<Tsit5, LogHalo, false, false>",
+                "flops_per_attempt": fpa, "attempts_per_launch": attempts,
+                "ms_per_launch": round(ms_kernel, 4),
+                "critical_path": {"max_attempts_one_orbit": max_att,
+                                  "lone_wave_us_per_attempt": round(us_per_attempt, 4),
+                                  "bound_ms": round(bound_ms, 3),
+                                  "frac_of_bound": round(bound_ms / ms_kernel, 3)}}
+
+    # The same kernel with the chip full: 10^6 uniform orbits.
+    nt = 1_000_000
+    tw = inputs.orbits_uneven(n=nt, seed=6)
+    tprob = api.make_problem(tw["rhs"], "tsit5", tw["y0"], tw["theta"], 0.0, np.full(nt, 20.0),
+                             np.full(nt, 1e-8), np.full(nt, 1e-8))
+    tsol = api.Solution(tprob, api.Launch(block=256, refill=16))
+    ms_t = timed(lambda: tsol.run(), 3, 1, torch)
+    att_t = int((tsol.n_accepted + tsol.n_rejected).to(torch.int64).sum())
+    ach_t = att_t * fpa / (ms_t * 1e-3) / 1e12
+    throughput = {"workload": "1,000,000 orbits, t = 20, rtol = atol = 1e-8, Tsit5",
+                  "ms": round(ms_t, 3), "attempts": att_t, "achieved": round(ach_t, 3),
+                  "unit": "TFLOP/s", "frac": round(ach_t / PEAK_FP64_VECTOR_TFLOPS, 4)}
+    log(f"[bench] kernel {ms_kernel:.3f} ms = {achieved:.2f} TFLOP/s; lone wave "
+        f"{us_per_attempt:.3f} us/attempt -> bound {bound_ms:.2f} ms; full chip "
+        f"{ach_t:.2f} TFLOP/s")
+
     out = {
         "metric": "solves/s + accepted RK steps/s at fixed error; grad/forward time ratio",
         "value": n / (ms * 1e-3),
@@ -163,12 +259,14 @@ def main():
         "data": "synthetic",
         "config": {"workload": "orbits_uneven_100k", "n": n, "rhs": "loghalo",
                    "tableau": "tsit5", "rtol": "logU[1e-9,1e-6]", "t_end": "logU[10,500]",
-                   "launch": "persistent queue, longest-first, hipGraph"},
+                   "launch": "persistent queue, longest-first, hipGraph, autotuned",
+                   "block": launch.block, "grid": launch.grid, "refill": launch.refill},
         "accepted_steps_per_s": nacc / (ms * 1e-3),
         "attempts_per_s": attempts / (ms * 1e-3),
-        "max_attempts_one_orbit": max_att,
+        "all_trajectories_ok": ok,
         "device": dev_name,
         "roofline": roofline,
+        "roofline_full_chip": throughput,
     }
 
     # ---- the other two arms of the same batch -------------------------------------------
@@ -205,6 +303,7 @@ def main():
         ms_fwd = timed(lambda: plain.run(), max(3, args.steps // 4), 1, torch)
         T = torch.as_tensor(wg["targets"], device="cuda")
         best = None
+        per_k = {}
         for k in (8, 32, 128):
             cap = int(plain.n_accepted.max()) // k + 2
             taped = api.Solution(pg, api.Launch(block=256, ckpt_every=k, ckpt_capacity=cap))
@@ -216,11 +315,13 @@ def main():
                 api.solve_vjp(taped, ybar_final=ybf)
 
             ms_g = timed(grad_step, max(3, args.steps // 4), 1, torch)
-            log(f"[bench] gradient k={k}: {ms_g:.3f} ms (forward {ms_fwd:.3f} ms)")
+            per_k[k] = round(ms_g, 4)
             if best is None or ms_g < best[1]:
                 best = (k, ms_g)
+        log(f"[bench] gradient: forward {ms_fwd:.3f} ms, with tape + adjoint {per_k}")
         out["grad"] = {"workload": "orbits_gradient_100k", "ms_forward": round(ms_fwd, 4),
-                       "ms_forward_tape_plus_vjp": round(best[1], 4), "ckpt_every": best[0]}
+                       "ms_forward_tape_plus_vjp": round(best[1], 4), "ckpt_every": best[0],
+                       "ms_by_ckpt_every": per_k}
         out["grad_forward_ratio"] = best[1] / ms_fwd
 
     if not args.no_cpu:
