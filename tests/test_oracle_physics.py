@@ -213,3 +213,37 @@ def test_tight_reference_self_consistency(orc):
     a = orc.solve(w["rhs"], "verner7", w["y0"], w["theta"], 0.0, 50.0, 1e-13, 1e-13, w["t_out"])
     b = orc.solve(w["rhs"], "verner7", w["y0"], w["theta"], 0.0, 50.0, 1e-12, 1e-12, w["t_out"])
     assert np.max(np.abs(a["y_out"] - b["y_out"])) < 1e-5 / 10
+
+
+def test_precession_matches_paper_accuracy_and_cost(orc):
+    """Against the figures the paper prints for its own precession setting
+    (r = 100 M to 10 M; Section "Spin precession", eq:prec-err): the 99th
+    percentile of the angle error of Verner 7 at 3.16e-9 and of Tsit5 at
+    5.62e-10 and 1e-9, the mean number of Verner 7 step attempts, and the
+    outcome of the tolerance selection (Verner 7 at 3.16e-9 and Tsit5 at
+    5.62e-10 pass the 2e-7 rad budget, Tsit5 at 1e-9 does not).  600
+    binaries drawn as in the paper; the reference is Verner 7 at 1e-13."""
+    import json
+    import os
+    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "precession_r100.json")))
+    w = inputs.spin_precession(n=600, seed=31)
+    t0 = 100.0 ** -0.5
+    ref = orc.solve("spinprec", "verner7", w["y0"], w["theta"], t0, w["t1"], 1e-13, 1e-13)
+
+    def p99(tab, tol):
+        a = orc.solve("spinprec", tab, w["y0"], w["theta"], t0, w["t1"], tol, tol)
+        eps = np.zeros(600)
+        for s in range(3):
+            x, y = a["y_final"][3 * s:3 * s + 3], ref["y_final"][3 * s:3 * s + 3]
+            ang = np.arctan2(np.linalg.norm(np.cross(x, y, axis=0), axis=0), np.sum(x * y, axis=0))
+            eps = np.maximum(eps, ang)
+        return np.quantile(eps, 0.99), np.mean(a["n_accepted"] + a["n_rejected"])
+
+    v, v_att = p99("verner7", g["verner7_rtol"])
+    t, _ = p99("tsit5", g["tsit5_rtol"])
+    tl, _ = p99("tsit5", g["tsit5_looser_rtol"])
+    assert abs(v_att / g["verner7_mean_attempts"] - 1) < 0.03
+    for got, want in ((v, g["verner7_p99_rad"]), (t, g["tsit5_p99_rad"]),
+                      (tl, g["tsit5_looser_p99_rad"])):
+        assert abs(got / want - 1) < 0.15, (got, want)
+    assert v < g["budget_rad"] and t < g["budget_rad"] < tl
