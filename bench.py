@@ -304,7 +304,7 @@ def main():
         T = torch.as_tensor(wg["targets"], device="cuda")
         best = None
         per_k = {}
-        for k in (8, 32, 128):
+        for k in (1, 8, 32, 128):
             cap = int(plain.n_accepted.max()) // k + 2
             taped = api.Solution(pg, api.Launch(block=256, ckpt_every=k, ckpt_capacity=cap))
             ybf = torch.zeros((1, 6, pg.n), dtype=torch.float64, device="cuda")

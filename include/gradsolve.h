@@ -132,9 +132,17 @@ typedef struct gs_solve_args {
                             starting-step rule                              */
   gs_controller ctrl;
 
-  /* Gradient tape: a checkpoint (t, h, err_prev, y, f(t, y)) every
-     ckpt_every accepted steps, ckpt_capacity of them per trajectory.
-     ckpt_every = 0 keeps no tape (no gradient, no dense query). */
+  /* Gradient tape (the store-or-recompute choice of eq:cost), up to
+     ckpt_capacity records per trajectory:
+       ckpt_every = 0   no tape (no gradient; dense queries replay from t0);
+       ckpt_every = 1   store mode: (t_n, h_{n-1}, y_n) of every accepted
+                        step, n = 0..N, so capacity >= N + 1; the adjoint
+                        and dense queries replay nothing;
+       ckpt_every >= 2  checkpoint mode: (t, h, err_prev, y, f(t, y)) every
+                        ckpt_every accepted steps; the adjoint replays each
+                        segment, so capacity >= N / ckpt_every + 1.
+     A trajectory that needs more records ends with GS_TRAJ_TAPE_OVERFLOW
+     (its solution is still complete). */
   int32_t ckpt_every;
   int32_t ckpt_capacity;
 
@@ -156,8 +164,9 @@ typedef struct gs_solve_args {
   void* stream;          /* hipStream_t                                     */
 } gs_solve_args;
 
-/* Cotangents for gs_solve_vjp.  R independent scalar losses share one replay:
- * for each r, ybar_out[r] = dL_r/dy(t_k) and ybar_final[r] = dL_r/dy(t1). */
+/* Cotangents for gs_solve_vjp.  R independent scalar losses over the same
+ * tape, one adjoint launch each: for each r, ybar_out[r] = dL_r/dy(t_k) and
+ * ybar_final[r] = dL_r/dy(t1). */
 typedef struct gs_vjp_args {
   int32_t R;                /* 1 <= R <= 8                                  */
   const double* ybar_out;   /* [R][d][K][n] or NULL                         */
@@ -176,9 +185,12 @@ typedef struct gs_vjp_args {
 void gs_default_args(gs_solve_args* args);
 
 /* Bytes of workspace `args` needs: the work-queue counters, the tape
- * (n * ckpt_capacity checkpoints of 3 + 2d doubles) and the adjoint's
- * per-lane replay scratch (ckpt_every steps of 2 + d doubles per lane).
- * Returns 0 for an invalid `args`. */
+ * (n * ckpt_capacity records of 2 + d doubles in store mode, 3 + 2d in
+ * checkpoint mode) and, with a tape, the adjoint's per-lane buffers for
+ * min(n rounded up to 256, 131072) lanes: the stage points of one step (s d
+ * doubles, s the tableau's stage count) and, in checkpoint mode, the replay
+ * scratch (ckpt_every steps of 2 + d doubles).  Returns 0 for an invalid
+ * `args`. */
 size_t gs_workspace_bytes(const gs_solve_args* args);
 
 /* Integrate every trajectory from t0 to t1 (eq:rk .. eq:dense), writing
@@ -192,7 +204,8 @@ gs_status gs_solve(const gs_solve_args* args);
  *   y0bar[r]    = sum_k ybar_out[r][k] S_y0(t_k)    + ybar_final[r] S_y0(t1)
  *   thetabar[r] = sum_k ybar_out[r][k] S_theta(t_k) + ybar_final[r] S_theta(t1)
  * where S are the forward sensitivities of eq:stage-sens along the accepted
- * steps.  Segments between checkpoints are recomputed bit-identically.
+ * steps.  In checkpoint mode the segments between checkpoints are
+ * recomputed bit-identically; store mode reads every step from the tape.
  * Trajectories whose status is not GS_TRAJ_OK get NaN cotangents. */
 gs_status gs_solve_vjp(const gs_solve_args* fwd, const gs_vjp_args* vjp);
 

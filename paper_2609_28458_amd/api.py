@@ -250,6 +250,14 @@ class Launch:
     beta2: float = 0.0
 
 
+def workspace_bytes(prob: Problem, launch: Launch) -> int:
+    """Device workspace a solve of `prob` with `launch` needs (gs_workspace_bytes)."""
+    a = gs_default_args()
+    a.rhs, a.tableau, a.n, a.d, a.p = prob.rhs, prob.tableau, prob.n, prob.d, NPARAM[prob.rhs]
+    a.ckpt_every, a.ckpt_capacity = launch.ckpt_every, launch.ckpt_capacity
+    return gs_workspace_bytes(a)
+
+
 class Solution:
     """Outputs and the buffers a later gradient or dense query reads."""
 

@@ -23,7 +23,7 @@ CACHE = os.environ.get("GS_AUTOTUNE_CACHE",
 
 BLOCKS = (64, 128, 256)
 REFILLS = (1, 16, 64)
-CKPT = (8, 32, 128)
+CKPT = (1, 8, 32, 128)  # 1 = store mode: every accepted step on the tape
 
 
 def _key(prob: api.Problem, kind: str) -> str:
@@ -111,8 +111,11 @@ def tune_gradient(prob: api.Problem, make_cotangent, base: api.Launch | None = N
     torch.cuda.synchronize()
     nmax = int(plain.n_accepted.max())
     best = None
+    free = torch.cuda.mem_get_info(prob.y0.device)[0]
     for k in CKPT:
         L = api.Launch(**{**base.__dict__, "ckpt_every": k, "ckpt_capacity": nmax // k + 2})
+        if api.workspace_bytes(prob, L) > free // 2:
+            continue  # the tape would crowd out everything else
         sol = api.Solution(prob, L)
 
         def step():

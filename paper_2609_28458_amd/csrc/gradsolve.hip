@@ -11,6 +11,7 @@
 
 #include "gradsolve.h"
 #include "gs_kernels.hpp"
+#include "gs_ops.hpp"
 
 namespace {
 
@@ -21,7 +22,16 @@ constexpr int kNumRhs = 5;
 constexpr int kNumTab = 3;
 constexpr int64_t kAdjMaxLanes = 131072;  // adjoint lanes on one GPU (2 waves per SIMD)
 constexpr size_t kCounterBytes = 256;
-constexpr int kVjpMaxR = 2;               // losses per adjoint launch
+// Losses per adjoint launch.  Each further loss is another launch; one loss
+// per lane keeps the adjoint kernels small enough to compile without
+// kilobytes of register spills for the largest right-hand sides.
+constexpr int kVjpMaxR = 1;
+
+// Clears the queue and replay counters at the head of the workspace (a
+// kernel rather than a memset, so a captured graph holds no memset node).
+__global__ void reset_counters_kernel(unsigned long long* c, int n) {
+  if ((int)threadIdx.x < n) c[threadIdx.x] = 0ull;
+}
 
 int rhs_dim(int r) {
   static const int d[kNumRhs] = {gs::Harmonic::D, gs::Kepler::D, gs::LogHalo::D,
@@ -34,10 +44,16 @@ int rhs_np(int r) {
   return p[r];
 }
 
+int tab_stages(int tab) {
+  static const int s[kNumTab] = {gs::Dopri5::S, gs::Tsit5::S, gs::Verner7::S};
+  return (tab >= 0 && tab < kNumTab) ? s[tab] : gs::Verner7::S;
+}
+
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 struct Layout {
-  size_t tape_off, tape_bytes, scratch_off, scratch_bytes, total;
+  size_t tape_off, tape_bytes, scratch_off, scratch_bytes, stages_off, stages_bytes, adj_off,
+      adj_bytes, total;
   int64_t adj_lanes;
 };
 
@@ -47,14 +63,26 @@ Layout layout_of(const gs_solve_args* a) {
   L.tape_off = kCounterBytes;
   L.tape_bytes = 0;
   L.scratch_bytes = 0;
+  L.stages_bytes = 0;
+  L.adj_bytes = 0;
   L.adj_lanes = 0;
   if (a->ckpt_every > 0) {
-    L.tape_bytes = (size_t)a->n * (size_t)a->ckpt_capacity * (size_t)(3 + 2 * d) * 8;
+    // Store mode (ckpt_every == 1) records (t, h, y) of every accepted step
+    // and needs no replay scratch; checkpoint mode records the controller
+    // state every ckpt_every steps and replays segments into scratch.
+    const bool store = a->ckpt_every == 1;
+    L.tape_bytes = (size_t)a->n * (size_t)a->ckpt_capacity * (size_t)(store ? 2 + d : 3 + 2 * d) * 8;
     L.adj_lanes = std::min<int64_t>((a->n + 255) / 256 * 256, kAdjMaxLanes);
-    L.scratch_bytes = (size_t)L.adj_lanes * (size_t)a->ckpt_every * (size_t)(2 + d) * 8;
+    L.scratch_bytes = store ? 0 : (size_t)L.adj_lanes * (size_t)a->ckpt_every * (size_t)(2 + d) * 8;
+    // Stage points of the step each adjoint lane is reversing.
+    L.stages_bytes = (size_t)L.adj_lanes * (size_t)tab_stages(a->tableau) * (size_t)d * 8;
+    // Running cotangents of y and theta for the losses of one launch.
+    L.adj_bytes = (size_t)L.adj_lanes * (size_t)kVjpMaxR * (size_t)(d + rhs_np(a->rhs)) * 8;
   }
   L.scratch_off = align256(L.tape_off + L.tape_bytes);
-  L.total = L.scratch_off + L.scratch_bytes;
+  L.stages_off = align256(L.scratch_off + L.scratch_bytes);
+  L.adj_off = align256(L.stages_off + L.stages_bytes);
+  L.total = L.adj_off + L.adj_bytes;
   return L;
 }
 
@@ -121,6 +149,7 @@ Params make_params(const gs_solve_args* a) {
   P.beta2 = a->ctrl.beta2;
   P.ckpt_every = a->ckpt_every;
   P.ckpt_cap = a->ckpt_capacity;
+  P.store = a->ckpt_every == 1 ? 1 : 0;
   const Layout L = layout_of(a);
   char* ws = static_cast<char*>(a->workspace);
   P.counters = reinterpret_cast<unsigned long long*>(ws);
@@ -147,63 +176,17 @@ int num_cus() {
   return cus > 0 ? cus : 256;
 }
 
-// Kernel launchers for one (tableau, right-hand side) pair.
-struct Ops {
-  const void* solve_fn;
-  void (*solve)(const Params&, int grid, int block, hipStream_t);
-  void (*vjp)(const Params&, const VjpParams&, int grid, int block, hipStream_t);
-  void (*dense)(const Params&, int32_t Q, const double*, double*, int grid, int block,
-                hipStream_t);
-};
+using gs_host::Ops;
 
-template <class TB, class F>
-void launch_solve(const Params& P, int grid, int block, hipStream_t s) {
-  if (P.K > 0) {
-    if (P.ckpt_every > 0)
-      hipLaunchKernelGGL((gs::solve_kernel<TB, F, true, true>), dim3(grid), dim3(block), 0, s, P);
-    else
-      hipLaunchKernelGGL((gs::solve_kernel<TB, F, true, false>), dim3(grid), dim3(block), 0, s, P);
-  } else {
-    if (P.ckpt_every > 0)
-      hipLaunchKernelGGL((gs::solve_kernel<TB, F, false, true>), dim3(grid), dim3(block), 0, s, P);
-    else
-      hipLaunchKernelGGL((gs::solve_kernel<TB, F, false, false>), dim3(grid), dim3(block), 0, s,
-                         P);
-  }
-}
-template <class TB, class F>
-void launch_vjp(const Params& P, const VjpParams& V, int grid, int block, hipStream_t s) {
-  if (V.R >= 2)
-    hipLaunchKernelGGL((gs::vjp_kernel<TB, F, 2>), dim3(grid), dim3(block), 0, s, P, V);
-  else
-    hipLaunchKernelGGL((gs::vjp_kernel<TB, F, 1>), dim3(grid), dim3(block), 0, s, P, V);
-}
-template <class TB, class F>
-void launch_dense(const Params& P, int32_t Q, const double* tq, double* yq, int grid, int block,
-                  hipStream_t s) {
-  hipLaunchKernelGGL((gs::dense_kernel<TB, F>), dim3(grid), dim3(block), 0, s, P, Q, tq, yq);
-}
-template <class TB, class F>
-Ops make_ops() {
-  return Ops{reinterpret_cast<const void*>(&gs::solve_kernel<TB, F, true, true>),
-             &launch_solve<TB, F>,
-             &launch_vjp<TB, F>, &launch_dense<TB, F>};
-}
-template <class F>
-void ops_row(Ops* row) {
-  row[GS_DOPRI5] = make_ops<gs::Dopri5, F>();
-  row[GS_TSIT5] = make_ops<gs::Tsit5, F>();
-  row[GS_VERNER7] = make_ops<gs::Verner7, F>();
-}
 const Ops& ops(int rhs, int tab) {
   static Ops table[kNumRhs][kNumTab];
   static std::once_flag once;
   std::call_once(once, [] {
-    ops_row<gs::Harmonic>(table[GS_RHS_HARMONIC]);
-    ops_row<gs::Kepler>(table[GS_RHS_KEPLER]);
-    ops_row<gs::LogHalo>(table[GS_RHS_LOGHALO]);
-    ops_row<gs::SpinPrec>(table[GS_RHS_SPINPREC]);
-    ops_row<gs::Quint>(table[GS_RHS_QUINT]);
+    gs_host::ops_row_harmonic(table[GS_RHS_HARMONIC]);
+    gs_host::ops_row_kepler(table[GS_RHS_KEPLER]);
+    gs_host::ops_row_loghalo(table[GS_RHS_LOGHALO]);
+    gs_host::ops_row_spinprec(table[GS_RHS_SPINPREC]);
+    gs_host::ops_row_quint(table[GS_RHS_QUINT]);
   });
   return table[rhs][tab];
 }
@@ -232,7 +215,7 @@ void solve_shape(const gs_solve_args* a, int* grid, int* block) {
 gs_status launch_solve_all(const gs_solve_args* a) {
   hipStream_t s = static_cast<hipStream_t>(a->stream);
   const Params P = make_params(a);
-  hipLaunchKernelGGL(gs::reset_counters_kernel, dim3(1), dim3(64), 0, s, P.counters, 4);
+  hipLaunchKernelGGL(reset_counters_kernel, dim3(1), dim3(64), 0, s, P.counters, 4);
   int grid = 0, block = 0;
   solve_shape(a, &grid, &block);
   ops(a->rhs, a->tableau).solve(P, grid, block, s);
@@ -284,23 +267,37 @@ gs_status gs_solve_vjp(const gs_solve_args* fwd, const gs_vjp_args* v) {
   if (fwd->n == 0) return GS_OK;
   const Layout L = layout_of(fwd);
   const int block = v->block > 0 ? v->block : 256;
-  int grid = (int)(L.adj_lanes / block);
-  if (v->grid > 0) grid = std::min(grid, v->grid);
-  if (grid < 1) return GS_ERR_INVALID;
   hipStream_t s = static_cast<hipStream_t>(v->stream);
   const Params P = make_params(fwd);
   VjpParams V;
+  std::memset(&V, 0, sizeof V);
+  V.R = std::min(kVjpMaxR, (int)v->R);
+  // Persistent grid: at most the lanes the workspace has scratch for, and no
+  // more than fit on the device at once.
+  int grid = (int)(L.adj_lanes / block);
+  if (v->grid > 0) {
+    grid = std::min(grid, v->grid);
+  } else {
+    int per_cu = 0;
+    V.occupancy_out = &per_cu;
+    ops(fwd->rhs, fwd->tableau).vjp(P, V, 0, block, s);
+    V.occupancy_out = nullptr;
+    if (per_cu > 0) grid = (int)std::min<int64_t>(grid, (int64_t)per_cu * num_cus());
+  }
+  if (grid < 1) return GS_ERR_INVALID;
   V.R_total = v->R;
   V.ybar_out = v->ybar_out;
   V.ybar_final = v->ybar_final;
   V.y0bar = v->y0bar;
   V.thetabar = v->thetabar;
   V.scratch = reinterpret_cast<double*>(static_cast<char*>(fwd->workspace) + L.scratch_off);
-  hipLaunchKernelGGL(gs::reset_counters_kernel, dim3(1), dim3(64), 0, s, P.counters + 2, 1);
+  V.stages = reinterpret_cast<double*>(static_cast<char*>(fwd->workspace) + L.stages_off);
+  V.adj = reinterpret_cast<double*>(static_cast<char*>(fwd->workspace) + L.adj_off);
+  hipLaunchKernelGGL(reset_counters_kernel, dim3(1), dim3(64), 0, s, P.counters + 2, 1);
   for (int r0 = 0; r0 < v->R; r0 += kVjpMaxR) {
     V.r0 = r0;
     V.R = std::min(kVjpMaxR, v->R - r0);
-    hipLaunchKernelGGL(gs::reset_counters_kernel, dim3(1), dim3(64), 0, s, P.counters + 1, 1);
+    hipLaunchKernelGGL(reset_counters_kernel, dim3(1), dim3(64), 0, s, P.counters + 1, 1);
     ops(fwd->rhs, fwd->tableau).vjp(P, V, grid, block, s);
   }
   return hipGetLastError() == hipSuccess ? GS_OK : GS_ERR_HIP;

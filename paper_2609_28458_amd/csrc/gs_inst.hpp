@@ -1,0 +1,74 @@
+// Instantiation of every kernel variant for one right-hand side (included by
+// the gs_inst_<rhs>.hip translation units only).
+#pragma once
+
+#include "gradsolve.h"
+#include "gs_ops.hpp"
+
+namespace gs_host {
+
+template <class TB, class F>
+void launch_solve(const gs::Params& P, int grid, int block, hipStream_t s) {
+  if (P.K > 0) {
+    if (P.ckpt_every > 0)
+      hipLaunchKernelGGL((gs::solve_kernel<TB, F, true, true>), dim3(grid), dim3(block), 0, s, P);
+    else
+      hipLaunchKernelGGL((gs::solve_kernel<TB, F, true, false>), dim3(grid), dim3(block), 0, s, P);
+  } else {
+    if (P.ckpt_every > 0)
+      hipLaunchKernelGGL((gs::solve_kernel<TB, F, false, true>), dim3(grid), dim3(block), 0, s, P);
+    else
+      hipLaunchKernelGGL((gs::solve_kernel<TB, F, false, false>), dim3(grid), dim3(block), 0, s,
+                         P);
+  }
+}
+
+template <class TB, class F, bool NODES, bool STORE>
+void launch_vjp_r(const gs::Params& P, const gs::VjpParams& V, int grid, int block,
+                  hipStream_t s) {
+  const void* fn = reinterpret_cast<const void*>(&gs::vjp_kernel<TB, F, 1, NODES, STORE>);
+  if (grid <= 0) {
+    // Occupancy query: blocks per CU of the variant that would launch.
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, block, 0) != hipSuccess) per_cu = 0;
+    *V.occupancy_out = per_cu;
+    return;
+  }
+  hipLaunchKernelGGL((gs::vjp_kernel<TB, F, 1, NODES, STORE>), dim3(grid), dim3(block), 0, s, P, V);
+}
+
+template <class TB, class F>
+void launch_vjp(const gs::Params& P, const gs::VjpParams& V, int grid, int block, hipStream_t s) {
+  if (P.K > 0) {
+    if (P.store)
+      launch_vjp_r<TB, F, true, true>(P, V, grid, block, s);
+    else
+      launch_vjp_r<TB, F, true, false>(P, V, grid, block, s);
+  } else {
+    if (P.store)
+      launch_vjp_r<TB, F, false, true>(P, V, grid, block, s);
+    else
+      launch_vjp_r<TB, F, false, false>(P, V, grid, block, s);
+  }
+}
+
+template <class TB, class F>
+void launch_dense(const gs::Params& P, int32_t Q, const double* tq, double* yq, int grid,
+                  int block, hipStream_t s) {
+  hipLaunchKernelGGL((gs::dense_kernel<TB, F>), dim3(grid), dim3(block), 0, s, P, Q, tq, yq);
+}
+
+template <class TB, class F>
+Ops make_ops() {
+  return Ops{reinterpret_cast<const void*>(&gs::solve_kernel<TB, F, true, true>),
+             &launch_solve<TB, F>, &launch_vjp<TB, F>, &launch_dense<TB, F>};
+}
+
+template <class F>
+void fill_row(Ops* row) {
+  row[GS_DOPRI5] = make_ops<gs::Dopri5, F>();
+  row[GS_TSIT5] = make_ops<gs::Tsit5, F>();
+  row[GS_VERNER7] = make_ops<gs::Verner7, F>();
+}
+
+}  // namespace gs_host

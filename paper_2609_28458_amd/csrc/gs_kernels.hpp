@@ -11,7 +11,12 @@
 //   outputs inside a step      eq:dense (polynomial), or a shortened step
 //                              from the start of the step for Verner 7
 // The derivative is the transpose of eq:stage-sens (reverse mode, steps held
-// fixed), computed by replaying each checkpointed segment.
+// fixed), computed backwards over a tape that stores every accepted step or
+// checkpoints from which segments are replayed (eq:cost).
+//
+// Wave-level votes (ballots) appear only where every lane of the wavefront
+// executes them; values that steer a whole wave are made scalar with
+// readfirstlane.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -83,7 +88,8 @@ struct Params {
   double safety, amin, amax, beta1, beta2;
   int32_t ckpt_every;
   int32_t ckpt_cap;
-  double* tape;                 // [n][ckpt_cap][3 + 2 d]
+  int32_t store;                // ckpt_every == 1: every accepted step is on the tape
+  double* tape;                 // [n][ckpt_cap][record], record as in tape_record
   unsigned long long* counters; // [0] forward queue, [1] adjoint queue, [2] replay mismatches
   const int64_t* order;
   int32_t refill;
@@ -99,7 +105,11 @@ struct VjpParams {
   const double* ybar_final;
   double* y0bar;
   double* thetabar;
-  double* scratch;     // [lanes][ckpt_every][2 + d]
+  double* scratch;     // [lanes / 64][ckpt_every][2 + d][64], checkpoint mode only
+  double* stages;      // [lanes / 64][s][d][64], stage points of the step being reversed
+  double* adj;         // [lanes / 64][R][d + p][64], running cotangents of each lane
+                       // (the launcher runs R = 1 per launch)
+  int* occupancy_out;  // host-side, for the launcher's occupancy query only
 };
 
 __device__ __forceinline__ double node_time(const Params& P, int kk, int64_t i) {
@@ -445,10 +455,31 @@ __device__ __forceinline__ Attempt attempt(const Params& P, Traj<TB, F>& s,
   return a;
 }
 
+// Tape records of trajectory i.  Checkpoint mode (ckpt_every >= 2): record c
+// holds (t, h, err_prev2, y, f(t, y)) after c * ckpt_every accepted steps, all
+// a replay needs to restart the controller.  Store mode (ckpt_every == 1):
+// record n holds (t_n, h_{n-1}, y_n) for n = 0..N, the start of every
+// accepted step and the length of the step that led to it, so the adjoint
+// and dense queries need no replay.
+template <class F>
+__host__ __device__ constexpr int ckpt_record_len() { return 3 + 2 * F::D; }
+template <class F>
+__host__ __device__ constexpr int store_record_len() { return 2 + F::D; }
+
 template <class TB, class F>
 __device__ __forceinline__ double* tape_record(const Params& P, int64_t i, int c) {
-  constexpr int REC = 3 + 2 * F::D;
-  return P.tape + ((int64_t)i * P.ckpt_cap + c) * REC;
+  const int rec = P.store ? store_record_len<F>() : ckpt_record_len<F>();
+  return P.tape + ((int64_t)i * P.ckpt_cap + c) * rec;
+}
+
+template <class TB, class F>
+__device__ __forceinline__ void write_store_record(const Params& P, int64_t i, int n, double t,
+                                                   double h_in, const double (&y)[F::D]) {
+  double* r = P.tape + ((int64_t)i * P.ckpt_cap + n) * store_record_len<F>();
+  r[0] = t;
+  r[1] = h_in;
+#pragma unroll
+  for (int j = 0; j < F::D; ++j) r[2 + j] = y[j];
 }
 
 template <class TB, class F>
@@ -478,6 +509,14 @@ __device__ __forceinline__ void read_checkpoint(const Params& P, int64_t i, int 
     s.k[0][j] = r[3 + F::D + j];
   }
   s.nanrun = 0;
+}
+
+// Lane 0's value in every lane, as a scalar the compiler knows is uniform,
+// so branches on it are uniform (no ballot ever sits in a divergent region).
+__device__ __forceinline__ unsigned long long first_lane(unsigned long long x) {
+  const unsigned lo = __builtin_amdgcn_readfirstlane(static_cast<unsigned>(x));
+  const unsigned hi = __builtin_amdgcn_readfirstlane(static_cast<unsigned>(x >> 32));
+  return (static_cast<unsigned long long>(hi) << 32) | lo;
 }
 
 __device__ __forceinline__ uint64_t lanemask_lt() {
@@ -565,10 +604,12 @@ __global__ void __launch_bounds__(256)
     s.h = P.h0 > 0.0 ? dmin(P.h0, s.in.t1 - s.in.t0) : initial_step<TB, F>(s.in, s.y, s.k[0]);
     s.ck_left = P.ckpt_every;
     if (TAPE) {
-      if (P.ckpt_cap > 0)
-        write_checkpoint<TB, F>(P, i, 0, s);
-      else
+      if (P.ckpt_cap <= 0)
         overflow = true;
+      else if (P.store)
+        write_store_record<TB, F>(P, i, 0, s.t, 0.0, s.y);
+      else
+        write_checkpoint<TB, F>(P, i, 0, s);
     }
   };
 
@@ -587,7 +628,7 @@ __global__ void __launch_bounds__(256)
       if (nidle >= P.refill) {
         unsigned long long base = 0;
         if (lane == 0) base = atomicAdd(P.counters, (unsigned long long)nidle);
-        base = __shfl(base, 0);
+        base = first_lane(base);
         if (base + (unsigned long long)nidle >= (unsigned long long)P.n) queue_empty = true;
         if (!live) {
           const unsigned long long pos = base + __popcll(idle & lanemask_lt());
@@ -628,9 +669,15 @@ __global__ void __launch_bounds__(256)
                   ++kp;
                 }
               });
-          if (a.finished) {
-            st = a.status;
-          } else if (TAPE) {
+          if (TAPE && P.store) {
+            // Every accepted step, the last one included.
+            if (a.accepted) {
+              if (s.nacc < P.ckpt_cap)
+                write_store_record<TB, F>(P, idx, s.nacc, s.t, a.h_used, s.y);
+              else
+                overflow = true;
+            }
+          } else if (TAPE && !a.finished) {
             s.ck_left -= a.accepted ? 1 : 0;
             if (s.ck_left == 0) {
               s.ck_left = P.ckpt_every;
@@ -641,6 +688,7 @@ __global__ void __launch_bounds__(256)
                 overflow = true;
             }
           }
+          if (a.finished) st = a.status;
         }
       }
       if (__ballot(live && st >= 0) != 0) break;
@@ -664,24 +712,28 @@ __host__ __device__ constexpr bool stage_feeds_step(int j) {
 // Reverse of one explicit RK step of length h from (t, y) (the transpose of
 // eq:stage-sens with h fixed).  lam[r] enters as the cotangent of y+ and
 // leaves as the cotangent of y; thb[r] accumulates the parameter cotangent.
-// An interior output of a polynomial-dense pair (has_node) adds
-// h b_j(sigma) g to the stage cotangents and g to the cotangent of y.
-template <class TB, class F, int R>
+// seed(r, kb, yb) adds the cotangents of outputs inside the step: for a
+// polynomial dense pair an output at sigma with cotangent g adds
+// h b_j(sigma) g to stage j and g to y.  all_stages also reverses the stages
+// that only the dense output reads.
+//
+// The stage points Y_j are recomputed first and parked in the lane's slice
+// of a per-wave buffer (ysc, component stride 64 so a wave touches whole
+// 512-byte rows), which keeps only the stage cotangents in registers.
+template <class TB, class F, int R, class Seed>
 __device__ __forceinline__ void reverse_step(const Inputs<F>& in, double t, double h,
                                              const double (&y)[F::D], double (&lam)[R][F::D],
-                                             double (&thb)[R][F::P], bool has_node, double sg,
-                                             const double (&gq)[R][F::D]) {
+                                             double (&thb)[R][F::P], bool all_stages,
+                                             Seed&& seed, double* ysc) {
   constexpr int S = TB::S, D = F::D;
-  // Recompute the stage points Y_j.
-  double Y[S][D];
+  auto Ys = [&](int j, int c) -> double& { return ysc[(j * D + c) * 64]; };
   {
     double k[S][D];
-#pragma unroll
-    for (int c = 0; c < D; ++c) Y[0][c] = y[c];
     F::f(t, y, in.par, k[0]);
     sfor<S - 1>([&](auto J1) {
       constexpr int j = decltype(J1)::value + 1;
-      if (stage_feeds_step<TB>(j) || (TB::POLY_DENSE && has_node)) {
+      if (stage_feeds_step<TB>(j) || (TB::POLY_DENSE && all_stages)) {
+        double Yj[D];
 #pragma unroll
         for (int c = 0; c < D; ++c) {
           double acc = 0.0;
@@ -690,9 +742,10 @@ __device__ __forceinline__ void reverse_step(const Inputs<F>& in, double t, doub
             constexpr double a = TB::A(j, l);
             if constexpr (a != 0.0) acc = fma(a, k[l][c], acc);
           });
-          Y[j][c] = fma(h, acc, y[c]);
+          Yj[c] = fma(h, acc, y[c]);
+          Ys(j, c) = Yj[c];
         }
-        if constexpr (j < S - 1) F::f(t + TB::C(j) * h, Y[j], in.par, k[j]);
+        if constexpr (j < S - 1) F::f(t + TB::C(j) * h, Yj, in.par, k[j]);
       }
     });
   }
@@ -708,28 +761,19 @@ __device__ __forceinline__ void reverse_step(const Inputs<F>& in, double t, doub
     });
 #pragma unroll
     for (int c = 0; c < D; ++c) yb[c] = lam[r][c];
-    if constexpr (TB::POLY_DENSE) {
-      if (has_node) {
-        sfor<S>([&](auto J) {
-          constexpr int j = decltype(J)::value;
-          double w = 0.0;
-          rfor<TB::DEG>([&](auto Q) {
-            constexpr int qq = decltype(Q)::value;
-            w = fma(w, sg, TB::Bs(j, qq));
-          });
-          w *= sg * h;
-#pragma unroll
-          for (int c = 0; c < D; ++c) kb[j][c] = fma(w, gq[r][c], kb[j][c]);
-        });
-#pragma unroll
-        for (int c = 0; c < D; ++c) yb[c] += gq[r][c];
-      }
-    }
+    seed(r, kb, yb);
     rfor<S>([&](auto J) {
       constexpr int j = decltype(J)::value;
-      if (stage_feeds_step<TB>(j) || (TB::POLY_DENSE && has_node)) {
-        double ybj[D];
-        F::vjp(t + TB::C(j) * h, Y[j], in.th, in.par, kb[j], ybj, thb[r]);
+      if (stage_feeds_step<TB>(j) || (TB::POLY_DENSE && all_stages)) {
+        double Yj[D], ybj[D];
+        if constexpr (j == 0) {
+#pragma unroll
+          for (int c = 0; c < D; ++c) Yj[c] = y[c];
+        } else {
+#pragma unroll
+          for (int c = 0; c < D; ++c) Yj[c] = Ys(j, c);
+        }
+        F::vjp(t + TB::C(j) * h, Yj, in.th, in.par, kb[j], ybj, thb[r]);
 #pragma unroll
         for (int c = 0; c < D; ++c) yb[c] += ybj[c];
         sfor<j>([&](auto L) {
@@ -747,198 +791,306 @@ __device__ __forceinline__ void reverse_step(const Inputs<F>& in, double t, doub
   }
 }
 
-// Discrete adjoint.  For each trajectory, segments between checkpoints are
-// processed last to first: replay the segment from its checkpoint (the same
-// attempt function as the forward, so the same accepted steps), keep
-// (t_n, h_n, y_n) of every accepted step in per-lane scratch, then run the
-// reverse steps backwards, injecting output-node cotangents where they fall.
-template <class TB, class F, int R>
+// Discrete adjoint, persistent like the forward solve.  A lane holds one
+// trajectory and walks its tape backwards one segment at a time: in
+// checkpoint mode a segment is the ckpt_every accepted steps after a
+// checkpoint, replayed from it with the forward's own attempt function (so
+// the same steps, bit for bit) while (t_n, h_n, y_n) of every accepted step
+// goes to per-wave scratch; in store mode a segment is one step read from
+// the tape.  The segment's steps are then reversed last to first, output
+// node cotangents entering where their nodes fall.  Every lane of a wave
+// works on a segment at the same time, so the replay and reverse phases
+// never diverge; a lane whose trajectory is done takes the next one from the
+// queue at the segment boundary.
+//
+// Between steps a lane keeps only a few integers in registers.  The running
+// cotangents (lambda of y, and of theta) live in a per-wave buffer, loaded
+// at the start of a step and stored at its end, and the trajectory's inputs
+// are reloaded for every segment; nothing floating-point is carried in
+// registers across the divergent refill and finish code.  Every per-wave
+// buffer is laid out [field][lane] (component stride 64), so a wave moves
+// whole 512-byte rows.
+// STORE: the tape is in store mode (chosen by the host from ckpt_every), so
+// the kernel holds no replay state at all.
+constexpr int kStoreSegment = 32;
+template <class TB, class F, int R, bool NODES, bool STORE>
 __global__ void __launch_bounds__(256) vjp_kernel(Params P, VjpParams V) {
   constexpr int D = F::D, NP = F::P;
   constexpr int SREC = 2 + D;
+  constexpr int AREC = D + NP;  // running cotangents of one loss
   const int lane = threadIdx.x & 63;
-  const int64_t slot = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  double* scr = V.scratch + slot * (int64_t)P.ckpt_every * SREC;
-  for (;;) {
-    // One trajectory per lane per round; every lane of the wave asks together.
-    unsigned long long base = 0;
-    if (lane == 0) base = atomicAdd(P.counters + 1, 64ull);
-    base = __shfl(base, 0);
-    if (base >= (unsigned long long)P.n) break;
-    const unsigned long long pos = base + lane;
-    if (pos >= (unsigned long long)P.n) continue;
-    const int64_t i = (int64_t)pos;
-    Traj<TB, F> s;
-    double yfinal_unused[D];
-    load_inputs<F>(P, i, s.in, yfinal_unused);
-    const int32_t st = P.status[i];
-    const int32_t N = P.n_acc[i];
-    double lam[R][D], thb[R][NP];
+  const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  constexpr bool store = STORE;
+  // Steps per segment: the checkpoint interval, or in store mode a fixed
+  // stretch of the tape (inputs, refill and bookkeeping once per segment).
+  const int kseg = store ? kStoreSegment : P.ckpt_every;
+  double* scr = V.scratch + (store ? 0 : wave * (int64_t)kseg * SREC * 64 + lane);
+  double* ysc = V.stages + wave * (int64_t)TB::S * D * 64 + lane;
+  double* ast = V.adj + wave * (int64_t)R * AREC * 64 + lane;
+  auto LAM = [&](int r, int c) -> double& { return ast[(r * AREC + c) * 64]; };
+  auto THB = [&](int r, int c) -> double& { return ast[(r * AREC + D + c) * 64]; };
+
+  int64_t idx = -1;
+  bool live = false, ok = false;
+  bool queue_empty = false;  // wave-uniform
+  int32_t N = 0, cseg = -1, kp = -1;
+
+  auto gbar = [&](int r, int c, int kk) -> double {
+    return (V.ybar_out && r < V.R)
+               ? V.ybar_out[(((int64_t)(V.r0 + r) * D + c) * P.K + kk) * P.n + idx]
+               : 0.0;
+  };
+  // Nodes at t0 read y0 directly; then the results leave the lane.
+  auto finish = [&]() {
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      if (r < V.R) {
+#pragma unroll
+        for (int c = 0; c < D; ++c) {
+          double l = LAM(r, c);
+          for (int kk = kp; NODES && kk >= 0; --kk) l += gbar(r, c, kk);
+          V.y0bar[((int64_t)(V.r0 + r) * D + c) * P.n + idx] = ok ? l : __builtin_nan("");
+        }
+#pragma unroll
+        for (int c = 0; c < NP; ++c)
+          V.thetabar[((int64_t)(V.r0 + r) * NP + c) * P.n + idx] =
+              ok ? THB(r, c) : __builtin_nan("");
+      }
+    }
+    live = false;
+  };
+  auto start = [&](int64_t i) {
+    idx = i;
+    live = true;
+    N = P.n_acc[i];
+    ok = P.status[i] == ST_OK;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
 #pragma unroll
       for (int c = 0; c < D; ++c)
-        lam[r][c] = (V.ybar_final && r < V.R)
+        LAM(r, c) = (V.ybar_final && r < V.R)
                         ? V.ybar_final[((int64_t)(V.r0 + r) * D + c) * P.n + i]
                         : 0.0;
 #pragma unroll
-      for (int c = 0; c < NP; ++c) thb[r][c] = 0.0;
+      for (int c = 0; c < NP; ++c) THB(r, c) = 0.0;
     }
-    auto gbar = [&](int r, int c, int kk) -> double {
-      return (V.ybar_out && r < V.R)
-                 ? V.ybar_out[(((int64_t)(V.r0 + r) * D + c) * P.K + kk) * P.n + i]
-                 : 0.0;
-    };
-    int kp = P.K - 1;
-    bool replay_ok = true;
-    if (st == ST_OK) {
-      const int nseg = (N + P.ckpt_every - 1) / P.ckpt_every;
-      for (int cseg = nseg - 1; cseg >= 0; --cseg) {
-        const int m = min(P.ckpt_every, N - cseg * P.ckpt_every);
-        read_checkpoint<TB, F>(P, i, cseg, s);
-        s.nacc = cseg * P.ckpt_every;
-        s.nrej = 0;
-        int j = 0;
-        while (j < m) {
-          // Record the start of the attempt in slot j; it is kept if the
-          // attempt is accepted.
-          double* rec = scr + (int64_t)j * SREC;
+    kp = P.K - 1;
+    cseg = (N + kseg - 1) / kseg - 1;
+    if (!ok || cseg < 0) finish();
+  };
+
+  for (;;) {
+    if (!queue_empty) {
+      const uint64_t idle = __ballot(!live);
+      const int nidle = __popcll(idle);
+      if (nidle > 0) {
+        unsigned long long base = 0;
+        if (lane == 0) base = atomicAdd(P.counters + 1, (unsigned long long)nidle);
+        base = first_lane(base);
+        if (base + (unsigned long long)nidle >= (unsigned long long)P.n) queue_empty = true;
+        if (!live) {
+          const unsigned long long pos = base + __popcll(idle & lanemask_lt());
+          if (pos < (unsigned long long)P.n) start((int64_t)pos);
+        }
+      }
+    }
+    if (__ballot(live) == 0) {
+      if (queue_empty) break;
+      continue;
+    }
+    // This segment's inputs, on every lane (idle lanes read trajectory 0's,
+    // in bounds and unused), so they are defined on every path.
+    Traj<TB, F> s;
+    {
+      double y_unused[D];
+      load_inputs<F>(P, live ? idx : 0, s.in, y_unused);
+    }
+    // Steps of this lane's current segment.
+    const int m = live ? min(kseg, N - cseg * kseg) : 0;
+    if constexpr (!store) {
+      // Replay the segment from its checkpoint (idle lanes: record 0 of
+      // trajectory 0, likewise unused).
+      read_checkpoint<TB, F>(P, live ? idx : 0, live ? cseg : 0, s);
+      s.nacc = cseg * kseg;
+      s.nrej = 0;
+      int j = 0;
+      bool lost = false;  // the replay ended before m steps: not faithful
+      while (__ballot(live && j < m && !lost) != 0) {
+        // The forward's step limit bounds a replay that is not faithful.
+        lost = lost | (live && j < m && (int64_t)s.nacc + s.nrej >= P.max_steps);
+        if (live && j < m && !lost) {
+          double* rec = scr + (int64_t)j * SREC * 64;
           rec[0] = s.t;
 #pragma unroll
-          for (int c = 0; c < D; ++c) rec[2 + c] = s.y[c];
+          for (int c = 0; c < D; ++c) rec[(2 + c) * 64] = s.y[c];
           const Attempt a = attempt<TB, F>(
               P, s, [&](const Traj<TB, F>&, double, double, const double (&)[D]) {});
           if (a.accepted) {
-            rec[1] = a.h_used;
+            rec[64] = a.h_used;
             ++j;
           }
-          if (a.finished && j < m) break;  // cannot happen on a faithful replay
+          lost = a.finished && j < m;
         }
-        if (j < m) {
-          atomicAdd(P.counters + 2, 1ull);
-          replay_ok = false;
-          break;
-        }
-        // Bit-exact replay check against the next checkpoint.
-        if (cseg + 1 < nseg && cseg + 1 < P.ckpt_cap) {
-          const double* nxt = tape_record<TB, F>(P, i, cseg + 1);
-          bool same = true;
+      }
+      if (live) {
+        // Bit-exact check against the next checkpoint, or for the last
+        // segment against the forward's final state.
+        bool same = !lost;
+        if (!lost && (cseg + 1) * kseg < N) {
+          const double* nxt = tape_record<TB, F>(P, idx, cseg + 1);
 #pragma unroll
-          for (int c = 0; c < D; ++c) same = same && (nxt[3 + c] == s.y[c]);
-          if (!same) atomicAdd(P.counters + 2, 1ull);
-        }
-        for (int jj = m - 1; jj >= 0; --jj) {
-          const double* rec = scr + (int64_t)jj * SREC;
-          const double tn = rec[0], hn = rec[1];
-          double yn[D];
+          for (int c = 0; c < D; ++c) same = same & (nxt[3 + c] == s.y[c]);
+        } else if (!lost) {
 #pragma unroll
-          for (int c = 0; c < D; ++c) yn[c] = rec[2 + c];
-          const bool last_step = (cseg * P.ckpt_every + jj) == N - 1;
-          const double t_new = last_step ? s.in.t1 : tn + hn;
-          // Nodes at the end of the step read y+ itself.
-          while (kp >= 0 && node_time(P, kp, i) == t_new) {
+          for (int c = 0; c < D; ++c) same = same & (P.y_final[(int64_t)c * P.n + idx] == s.y[c]);
+        }
+        if (!same) atomicAdd(P.counters + 2, 1ull);
+        ok = ok & !lost;
+      }
+    }
+    // Reverse the segment's steps, last to first.  The record of step n
+    // holds (t_n, y_n) and, in store mode, h_{n-1} (replayed records hold
+    // h_n), so each step reads one record; the next step's record is
+    // fetched before this step's arithmetic.
+    const int fs = store ? 1 : 64;  // field stride of a record
+    auto record = [&](int jj) -> const double* {
+      return store ? tape_record<TB, F>(P, idx, cseg * kseg + jj) : scr + (int64_t)jj * SREC * 64;
+    };
+    double nx_t = 0.0, nx_h = 0.0, nx_y[D];
+    double h_carry = 0.0;  // store mode: h of the step about to be reversed
+    bool have = false;
+    for (int jj = kseg - 1; jj >= 0; --jj) {
+      const bool act = live && ok && jj < m;
+      if (__ballot(act) == 0) continue;
+      if (!act) continue;
+      if (!have) {
+        // First step of the segment on this lane.
+        const double* rec = record(jj);
+        nx_t = rec[0];
+        nx_h = rec[fs];
+#pragma unroll
+        for (int c = 0; c < D; ++c) nx_y[c] = rec[(2 + c) * fs];
+        if constexpr (store) h_carry = tape_record<TB, F>(P, idx, cseg * kseg + jj + 1)[1];
+        have = true;
+      }
+      const double tn = nx_t;
+      const double hn = store ? h_carry : nx_h;
+      double yn[D];
+#pragma unroll
+      for (int c = 0; c < D; ++c) yn[c] = nx_y[c];
+      if constexpr (store) h_carry = nx_h;
+      if (jj > 0) {
+        const double* rec = record(jj - 1);
+        nx_t = rec[0];
+        nx_h = rec[fs];
+#pragma unroll
+        for (int c = 0; c < D; ++c) nx_y[c] = rec[(2 + c) * fs];
+      }
+      const bool last_step = cseg * kseg + jj == N - 1;
+      const double t_new = last_step ? s.in.t1 : tn + hn;
+      double lam[R][D], thb[R][NP];
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+#pragma unroll
+        for (int c = 0; c < D; ++c) lam[r][c] = LAM(r, c);
+#pragma unroll
+        for (int c = 0; c < NP; ++c) thb[r][c] = THB(r, c);
+      }
+      auto no_seed = [](int, double(&)[TB::S][D], double(&)[D]) {};
+      if constexpr (!NODES) {
+        reverse_step<TB, F, R>(s.in, tn, hn, yn, lam, thb, false, no_seed, ysc);
+      } else {
+        // Nodes at the end of the step read y+ itself.
+        while (kp >= 0 && node_time(P, kp, idx) == t_new) {
+#pragma unroll
+          for (int r = 0; r < R; ++r)
+#pragma unroll
+            for (int c = 0; c < D; ++c) lam[r][c] += gbar(r, c, kp);
+          --kp;
+        }
+        // Nodes inside the step: indices kp, kp - 1, ..., k_lo + 1.
+        int k_lo = kp;
+        while (k_lo >= 0 && node_time(P, k_lo, idx) > tn) --k_lo;
+        if constexpr (TB::POLY_DENSE) {
+          // All of them enter one reverse pass: their cotangents are linear
+          // seeds of the stages, added while the stage cotangents are set
+          // up (a short per-lane loop), so the step itself is reversed once.
+          const int kp_top = kp;
+          const bool any = kp > k_lo;
+          auto seed = [&](int r, double (&kb)[TB::S][D], double (&yb)[D]) {
+            for (int kq = kp_top; kq > k_lo; --kq) {
+              const double sg = (node_time(P, kq, idx) - tn) / hn;
+              double g[D];
+#pragma unroll
+              for (int c = 0; c < D; ++c) g[c] = gbar(r, c, kq);
+              sfor<TB::S>([&](auto J) {
+                constexpr int j = decltype(J)::value;
+                double w = 0.0;
+                rfor<TB::DEG>([&](auto Q) {
+                  constexpr int qq = decltype(Q)::value;
+                  w = fma(w, sg, TB::Bs(j, qq));
+                });
+                w *= sg * hn;
+#pragma unroll
+                for (int c = 0; c < D; ++c) kb[j][c] = fma(w, g[c], kb[j][c]);
+              });
+#pragma unroll
+              for (int c = 0; c < D; ++c) yb[c] += g[c];
+            }
+          };
+          reverse_step<TB, F, R>(s.in, tn, hn, yn, lam, thb, any, seed, ysc);
+          kp = k_lo;
+        } else {
+          // Shortened-step outputs: each is a full step of length sigma h
+          // from y_n with its own stage points, so each takes a reverse pass
+          // of its own, before the step itself; their cotangents of y_n are
+          // summed with the step's.  One reverse_step call site: a lane
+          // passes through its nodes, then its step.
+          double acc[R][D];
+#pragma unroll
+          for (int r = 0; r < R; ++r)
+#pragma unroll
+            for (int c = 0; c < D; ++c) acc[r][c] = 0.0;
+          bool has;
+          do {
+            has = kp > k_lo;
+            const double hq = has ? ((node_time(P, kp, idx) - tn) / hn) * hn : hn;
+            double lz[R][D];
 #pragma unroll
             for (int r = 0; r < R; ++r)
 #pragma unroll
-              for (int c = 0; c < D; ++c) lam[r][c] += gbar(r, c, kp);
-            --kp;
-          }
-          double gq[R][D];
-          if constexpr (TB::POLY_DENSE) {
-            // The step's own cotangent together with its last interior node;
-            // further interior nodes of the same step enter with a zero
-            // cotangent for y+ and their results are summed.
-            bool first = true;
-            do {
-              const bool has = kp >= 0 && node_time(P, kp, i) > tn;
-              double sg = 0.0;
-              if (has) {
-                sg = (node_time(P, kp, i) - tn) / hn;
-#pragma unroll
-                for (int r = 0; r < R; ++r)
-#pragma unroll
-                  for (int c = 0; c < D; ++c) gq[r][c] = gbar(r, c, kp);
-                --kp;
-              } else {
-#pragma unroll
-                for (int r = 0; r < R; ++r)
-#pragma unroll
-                  for (int c = 0; c < D; ++c) gq[r][c] = 0.0;
-              }
-              if (first) {
-                reverse_step<TB, F, R>(s.in, tn, hn, yn, lam, thb, has, sg, gq);
-                first = false;
-              } else {
-                double lz[R][D];
-#pragma unroll
-                for (int r = 0; r < R; ++r)
-#pragma unroll
-                  for (int c = 0; c < D; ++c) lz[r][c] = 0.0;
-                reverse_step<TB, F, R>(s.in, tn, hn, yn, lz, thb, true, sg, gq);
-#pragma unroll
-                for (int r = 0; r < R; ++r)
-#pragma unroll
-                  for (int c = 0; c < D; ++c) lam[r][c] += lz[r][c];
-              }
-            } while (kp >= 0 && node_time(P, kp, i) > tn);
-          } else {
-            // Shortened-step outputs: each one is a full step of length
-            // sigma h from the start of the step, so its cotangent lands on
-            // y_n directly and is added after the step itself is reversed.
-            double lz[R][D], acc[R][D];
+              for (int c = 0; c < D; ++c) lz[r][c] = has ? gbar(r, c, kp) : lam[r][c];
+            reverse_step<TB, F, R>(s.in, tn, hq, yn, lz, thb, false, no_seed, ysc);
 #pragma unroll
             for (int r = 0; r < R; ++r)
 #pragma unroll
               for (int c = 0; c < D; ++c) {
-                acc[r][c] = 0.0;
-                gq[r][c] = 0.0;
+                acc[r][c] += has ? lz[r][c] : 0.0;
+                lam[r][c] = has ? lam[r][c] : lz[r][c] + acc[r][c];
               }
-            while (kp >= 0 && node_time(P, kp, i) > tn) {
-              const double hq = ((node_time(P, kp, i) - tn) / hn) * hn;
-#pragma unroll
-              for (int r = 0; r < R; ++r)
-#pragma unroll
-                for (int c = 0; c < D; ++c) lz[r][c] = gbar(r, c, kp);
-              reverse_step<TB, F, R>(s.in, tn, hq, yn, lz, thb, false, 0.0, gq);
-#pragma unroll
-              for (int r = 0; r < R; ++r)
-#pragma unroll
-                for (int c = 0; c < D; ++c) acc[r][c] += lz[r][c];
-              --kp;
-            }
-            reverse_step<TB, F, R>(s.in, tn, hn, yn, lam, thb, false, 0.0, gq);
-#pragma unroll
-            for (int r = 0; r < R; ++r)
-#pragma unroll
-              for (int c = 0; c < D; ++c) lam[r][c] += acc[r][c];
-          }
+            kp -= has ? 1 : 0;
+          } while (has);
         }
       }
-      // Nodes at t0 read y0 directly.
-      while (kp >= 0) {
 #pragma unroll
-        for (int r = 0; r < R; ++r)
+      for (int r = 0; r < R; ++r) {
 #pragma unroll
-          for (int c = 0; c < D; ++c) lam[r][c] += gbar(r, c, kp);
-        --kp;
+        for (int c = 0; c < D; ++c) LAM(r, c) = lam[r][c];
+#pragma unroll
+        for (int c = 0; c < NP; ++c) THB(r, c) = thb[r][c];
       }
     }
-    const bool ok = (st == ST_OK) && replay_ok;
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-      if (r >= V.R) break;
-#pragma unroll
-      for (int c = 0; c < D; ++c)
-        V.y0bar[((int64_t)(V.r0 + r) * D + c) * P.n + i] = ok ? lam[r][c] : __builtin_nan("");
-#pragma unroll
-      for (int c = 0; c < NP; ++c)
-        V.thetabar[((int64_t)(V.r0 + r) * NP + c) * P.n + i] = ok ? thb[r][c] : __builtin_nan("");
+    // Segment done.
+    if (live) {
+      cseg -= 1;
+      if (!ok || cseg < 0) finish();
     }
   }
 }
 
 // ---------------------------------------------------------------------------
-// Dense query: y(t_q) for Q times per trajectory, by replaying from the last
+// Dense query: y(t_q) for Q times per trajectory: in store mode from the
+// recorded step that contains t_q, otherwise by replaying from the last
 // checkpoint before t_q (or from t0 without a tape).
 template <class TB, class F>
 __global__ void __launch_bounds__(256) dense_kernel(Params P, int32_t Q, const double* tq_all,
@@ -964,6 +1116,40 @@ __global__ void __launch_bounds__(256) dense_kernel(Params P, int32_t Q, const d
     } else if (tq == s.in.t0) {
 #pragma unroll
       for (int c = 0; c < D; ++c) out[c] = y0[c];
+      done = true;
+    }
+    if (!done && P.store) {
+      // Store mode: the step containing tq is on the tape; take it once.
+      int lo = 0, hi = min(N, P.ckpt_cap - 1);
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) / 2;
+        if (tape_record<TB, F>(P, i, mid)[0] < tq)
+          lo = mid;
+        else
+          hi = mid - 1;
+      }
+      const double* rec = tape_record<TB, F>(P, i, lo);
+      const double* nxt = tape_record<TB, F>(P, i, lo + 1);
+      if (lo >= N || lo + 1 >= P.ckpt_cap) {
+#pragma unroll
+        for (int c = 0; c < D; ++c) out[c] = __builtin_nan("");
+      } else if (nxt[0] == tq) {
+#pragma unroll
+        for (int c = 0; c < D; ++c) out[c] = nxt[2 + c];
+      } else {
+        const double tn = rec[0], hn = nxt[1];
+#pragma unroll
+        for (int c = 0; c < D; ++c) s.y[c] = rec[2 + c];
+        F::f(tn, s.y, s.in.par, s.k[0]);
+        double yend[D];
+        if constexpr (TB::POLY_DENSE) {
+          rk_stages<TB, F>(s.in.par, tn, hn, s.y, s.k, yend);
+        } else {
+#pragma unroll
+          for (int c = 0; c < D; ++c) yend[c] = nxt[2 + c];
+        }
+        dense_value<TB, F>(s.in.par, tn, hn, (tq - tn) / hn, yend, s.y, s.k, out);
+      }
       done = true;
     }
     if (!done) {
@@ -1048,10 +1234,6 @@ __global__ void __launch_bounds__(256) rhs_kernel(int64_t m, const double* t, co
 #pragma unroll
     for (int c = 0; c < NP; ++c) thetabar[(int64_t)c * m + i] = tb[c];
   }
-}
-
-__global__ void reset_counters_kernel(unsigned long long* c, int n) {
-  if ((int)threadIdx.x < n) c[threadIdx.x] = 0ull;
 }
 
 }  // namespace gs

@@ -1,0 +1,30 @@
+// Kernel launchers of one (tableau, right-hand side) pair, and the tables
+// that the C ABI dispatches through.  Each right-hand side's kernels are
+// instantiated in a translation unit of their own (gs_inst_<rhs>.hip) so the
+// library builds in parallel.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "gs_kernels.hpp"
+
+namespace gs_host {
+
+struct Ops {
+  const void* solve_fn;  // a forward kernel, for the occupancy query
+  void (*solve)(const gs::Params&, int grid, int block, hipStream_t);
+  // grid <= 0: no launch; writes the blocks per CU of the variant that
+  // would run to *V.occupancy_out.
+  void (*vjp)(const gs::Params&, const gs::VjpParams&, int grid, int block, hipStream_t);
+  void (*dense)(const gs::Params&, int32_t Q, const double*, double*, int grid, int block,
+                hipStream_t);
+};
+
+// Fill row[GS_DOPRI5], row[GS_TSIT5], row[GS_VERNER7] for one right-hand side.
+void ops_row_harmonic(Ops* row);
+void ops_row_kepler(Ops* row);
+void ops_row_loghalo(Ops* row);
+void ops_row_spinprec(Ops* row);
+void ops_row_quint(Ops* row);
+
+}  // namespace gs_host

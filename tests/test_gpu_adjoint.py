@@ -53,18 +53,26 @@ def _fs_grad(o, d, ybar_out, ybar_final):
     return g[:d], g[d:]
 
 
+@pytest.mark.parametrize("nodes", [True, False], ids=["nodes", "final"])
+@pytest.mark.parametrize("k", [1, 5], ids=["store", "ckpt5"])
 @pytest.mark.parametrize("tab", ["dopri5", "tsit5", "verner7"])
 @pytest.mark.parametrize("name,make", CASES, ids=[c[0] for c in CASES])
-def test_vjp_matches_oracle_sensitivities(orc, name, make, tab):
+def test_vjp_matches_oracle_sensitivities(orc, name, make, tab, k, nodes):
+    """Every adjoint kernel variant against the oracle: store mode (every
+    accepted step on the tape, no replay) and checkpoint mode (replayed
+    segments of 5 steps), with output-node cotangents and with the final
+    state only."""
     w = make(150)
     w["tableau"] = tab
+    if not nodes:
+        w["t_out"] = None
     prob = _problem(w)
     d, n, K = prob.d, prob.n, prob.K
     p = api.NPARAM[prob.rhs]
     rng = np.random.default_rng(11)
-    ybo = rng.normal(size=(1, d, K, n))
+    ybo = rng.normal(size=(1, d, K, n)) if K else None
     ybf = rng.normal(size=(1, d, n))
-    sol = _solve_taped(prob, k=5)
+    sol = _solve_taped(prob, k=k, cap=20000 if k == 1 else None)
     assert np.all(sol.status.cpu().numpy() == 0)
     y0b, thb = api.solve_vjp(sol, ybar_final=ybf, ybar_out=ybo)
     torch.cuda.synchronize()
@@ -73,7 +81,7 @@ def test_vjp_matches_oracle_sensitivities(orc, name, make, tab):
         np.asarray(w["theta"])[:, None], n, axis=1)
     o = oracle_solve(orc, {**w, "theta": th}, sens_cols=list(range(d + p)))
     np.testing.assert_array_equal(sol.n_accepted.cpu().numpy(), o["n_accepted"])
-    gy, gt = _fs_grad(o, d, ybo[0], ybf[0])
+    gy, gt = _fs_grad(o, d, None if ybo is None else ybo[0], ybf[0])
     G = np.concatenate([y0b[0].cpu().numpy(), thb[0].cpu().numpy()])
     R = np.concatenate([gy, gt])
     scale = np.maximum(np.abs(R).max(axis=0), 1.0)
@@ -101,7 +109,7 @@ def test_checkpoint_interval_does_not_change_the_gradient():
             np.testing.assert_array_equal(got[1], ref[1])
 
 
-def test_several_losses_share_one_replay():
+def test_several_losses_match_single_calls():
     w = inputs.spin_precession(n=96, seed=52)
     w = {**w, "t0": 100 ** -0.5, "t_out": None}
     prob = _problem(w)
@@ -199,10 +207,11 @@ def test_gradient_config_full_size(orc):
         assert abs(tot_fd - tot_g) <= 1e-4 * abs(tot_g), (c, tot_fd, tot_g, excluded)
 
 
-def test_tape_overflow_is_reported():
+@pytest.mark.parametrize("k,cap", [(4, 3), (1, 12)], ids=["ckpt", "store"])
+def test_tape_overflow_is_reported(k, cap):
     w = inputs.orbits_forward(n=64, seed=53)
     prob = _problem(w)
-    sol = _solve_taped(prob, k=4, cap=3)
+    sol = _solve_taped(prob, k=k, cap=cap)
     st = sol.status.cpu().numpy()
     assert np.all(st == 4)
     y0b, thb = api.solve_vjp(sol, ybar_final=np.ones((1, 6, 64)))
@@ -214,12 +223,12 @@ def test_tape_overflow_is_reported():
 
 
 @pytest.mark.parametrize("tab", ["tsit5", "verner7"])
-@pytest.mark.parametrize("taped", [True, False])
+@pytest.mark.parametrize("taped", [0, 1, 7], ids=["untaped", "store", "ckpt7"])
 def test_dense_queries_match_oracle_nodes(orc, tab, taped):
     w = inputs.orbits_forward(n=200, seed=54)
     w = {**w, "tableau": tab, "t_out": None}
     prob = _problem(w)
-    sol = _solve_taped(prob, k=7) if taped else api.solve(prob)
+    sol = _solve_taped(prob, k=taped) if taped else api.solve(prob)
     torch.cuda.synchronize()
     rng = np.random.default_rng(14)
     tq = np.sort(rng.uniform(0.0, 50.0, (9, 200)), axis=0)
