@@ -187,10 +187,9 @@ void gs_default_args(gs_solve_args* args);
 /* Bytes of workspace `args` needs: the work-queue counters, the tape
  * (n * ckpt_capacity records of 2 + d doubles in store mode, 3 + 2d in
  * checkpoint mode) and, with a tape, the adjoint's per-lane buffers for
- * min(n rounded up to 256, 131072) lanes: the stage points of one step (s d
- * doubles, s the tableau's stage count) and, in checkpoint mode, the replay
- * scratch (ckpt_every steps of 2 + d doubles).  Returns 0 for an invalid
- * `args`. */
+ * min(n rounded up to 256, 131072) lanes: the running cotangents (d + p
+ * doubles) and, in checkpoint mode, the replay scratch (ckpt_every steps of
+ * 2 + d doubles).  Returns 0 for an invalid `args`. */
 size_t gs_workspace_bytes(const gs_solve_args* args);
 
 /* Integrate every trajectory from t0 to t1 (eq:rk .. eq:dense), writing

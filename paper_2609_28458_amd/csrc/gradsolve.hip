@@ -52,8 +52,7 @@ int tab_stages(int tab) {
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 struct Layout {
-  size_t tape_off, tape_bytes, scratch_off, scratch_bytes, stages_off, stages_bytes, adj_off,
-      adj_bytes, total;
+  size_t tape_off, tape_bytes, scratch_off, scratch_bytes, adj_off, adj_bytes, total;
   int64_t adj_lanes;
 };
 
@@ -63,7 +62,6 @@ Layout layout_of(const gs_solve_args* a) {
   L.tape_off = kCounterBytes;
   L.tape_bytes = 0;
   L.scratch_bytes = 0;
-  L.stages_bytes = 0;
   L.adj_bytes = 0;
   L.adj_lanes = 0;
   if (a->ckpt_every > 0) {
@@ -74,14 +72,11 @@ Layout layout_of(const gs_solve_args* a) {
     L.tape_bytes = (size_t)a->n * (size_t)a->ckpt_capacity * (size_t)(store ? 2 + d : 3 + 2 * d) * 8;
     L.adj_lanes = std::min<int64_t>((a->n + 255) / 256 * 256, kAdjMaxLanes);
     L.scratch_bytes = store ? 0 : (size_t)L.adj_lanes * (size_t)a->ckpt_every * (size_t)(2 + d) * 8;
-    // Stage points of the step each adjoint lane is reversing.
-    L.stages_bytes = (size_t)L.adj_lanes * (size_t)tab_stages(a->tableau) * (size_t)d * 8;
     // Running cotangents of y and theta for the losses of one launch.
     L.adj_bytes = (size_t)L.adj_lanes * (size_t)kVjpMaxR * (size_t)(d + rhs_np(a->rhs)) * 8;
   }
   L.scratch_off = align256(L.tape_off + L.tape_bytes);
-  L.stages_off = align256(L.scratch_off + L.scratch_bytes);
-  L.adj_off = align256(L.stages_off + L.stages_bytes);
+  L.adj_off = align256(L.scratch_off + L.scratch_bytes);
   L.total = L.adj_off + L.adj_bytes;
   return L;
 }
@@ -162,6 +157,18 @@ Params make_params(const gs_solve_args* a) {
                     ? 1
                     : 0;
   return P;
+}
+
+size_t max_lds_per_block() {
+  static int bytes = 0;
+  static std::once_flag once;
+  std::call_once(once, [] {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&bytes, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+      bytes = 0;
+  });
+  return bytes > 0 ? (size_t)bytes : 65536;
 }
 
 int num_cus() {
@@ -266,12 +273,19 @@ gs_status gs_solve_vjp(const gs_solve_args* fwd, const gs_vjp_args* v) {
     return GS_ERR_INVALID;
   if (fwd->n == 0) return GS_OK;
   const Layout L = layout_of(fwd);
-  const int block = v->block > 0 ? v->block : 256;
+  // The stage points of the step each lane reverses live in LDS, (s - 1) d
+  // doubles per lane; a block that would need more than the device allows
+  // per workgroup gets fewer lanes.
+  const size_t lds_lane = (size_t)(tab_stages(fwd->tableau) - 1) * rhs_dim(fwd->rhs) * 8;
+  int block = v->block > 0 ? v->block : 256;
+  while (block > 64 && lds_lane * block > max_lds_per_block()) block -= 64;
+  if (lds_lane * block > max_lds_per_block()) return GS_ERR_UNSUPPORTED;
   hipStream_t s = static_cast<hipStream_t>(v->stream);
   const Params P = make_params(fwd);
   VjpParams V;
   std::memset(&V, 0, sizeof V);
   V.R = std::min(kVjpMaxR, (int)v->R);
+  V.lds_bytes = (int32_t)(lds_lane * block);
   // Persistent grid: at most the lanes the workspace has scratch for, and no
   // more than fit on the device at once.
   int grid = (int)(L.adj_lanes / block);
@@ -291,7 +305,6 @@ gs_status gs_solve_vjp(const gs_solve_args* fwd, const gs_vjp_args* v) {
   V.y0bar = v->y0bar;
   V.thetabar = v->thetabar;
   V.scratch = reinterpret_cast<double*>(static_cast<char*>(fwd->workspace) + L.scratch_off);
-  V.stages = reinterpret_cast<double*>(static_cast<char*>(fwd->workspace) + L.stages_off);
   V.adj = reinterpret_cast<double*>(static_cast<char*>(fwd->workspace) + L.adj_off);
   hipLaunchKernelGGL(reset_counters_kernel, dim3(1), dim3(64), 0, s, P.counters + 2, 1);
   for (int r0 = 0; r0 < v->R; r0 += kVjpMaxR) {

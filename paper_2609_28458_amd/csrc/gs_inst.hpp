@@ -30,11 +30,13 @@ void launch_vjp_r(const gs::Params& P, const gs::VjpParams& V, int grid, int blo
   if (grid <= 0) {
     // Occupancy query: blocks per CU of the variant that would launch.
     int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, block, 0) != hipSuccess) per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, block, V.lds_bytes) != hipSuccess)
+      per_cu = 0;
     *V.occupancy_out = per_cu;
     return;
   }
-  hipLaunchKernelGGL((gs::vjp_kernel<TB, F, 1, NODES, STORE>), dim3(grid), dim3(block), 0, s, P, V);
+  hipLaunchKernelGGL((gs::vjp_kernel<TB, F, 1, NODES, STORE>), dim3(grid), dim3(block), V.lds_bytes,
+                     s, P, V);
 }
 
 template <class TB, class F>

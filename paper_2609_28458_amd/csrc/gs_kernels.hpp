@@ -106,7 +106,7 @@ struct VjpParams {
   double* y0bar;
   double* thetabar;
   double* scratch;     // [lanes / 64][ckpt_every][2 + d][64], checkpoint mode only
-  double* stages;      // [lanes / 64][s][d][64], stage points of the step being reversed
+  int32_t lds_bytes;   // host-side: dynamic LDS per block for the stage points
   double* adj;         // [lanes / 64][R][d + p][64], running cotangents of each lane
                        // (the launcher runs R = 1 per launch)
   int* occupancy_out;  // host-side, for the launcher's occupancy query only
@@ -717,16 +717,17 @@ __host__ __device__ constexpr bool stage_feeds_step(int j) {
 // h b_j(sigma) g to stage j and g to y.  all_stages also reverses the stages
 // that only the dense output reads.
 //
-// The stage points Y_j are recomputed first and parked in the lane's slice
-// of a per-wave buffer (ysc, component stride 64 so a wave touches whole
-// 512-byte rows), which keeps only the stage cotangents in registers.
+// The stage points Y_1 .. Y_{s-1} are recomputed first and parked in the
+// lane's slice of LDS (ysc, stride `ys` between values, so the lanes of a
+// workgroup touch consecutive words), which keeps only the stage
+// cotangents in registers and the stage points off HBM.
 template <class TB, class F, int R, class Seed>
 __device__ __forceinline__ void reverse_step(const Inputs<F>& in, double t, double h,
                                              const double (&y)[F::D], double (&lam)[R][F::D],
                                              double (&thb)[R][F::P], bool all_stages,
-                                             Seed&& seed, double* ysc) {
+                                             Seed&& seed, double* ysc, int ys) {
   constexpr int S = TB::S, D = F::D;
-  auto Ys = [&](int j, int c) -> double& { return ysc[(j * D + c) * 64]; };
+  auto Ys = [&](int j, int c) -> double& { return ysc[((j - 1) * D + c) * ys]; };
   {
     double k[S][D];
     F::f(t, y, in.par, k[0]);
@@ -803,13 +804,14 @@ __device__ __forceinline__ void reverse_step(const Inputs<F>& in, double t, doub
 // never diverge; a lane whose trajectory is done takes the next one from the
 // queue at the segment boundary.
 //
-// Between steps a lane keeps only a few integers in registers.  The running
-// cotangents (lambda of y, and of theta) live in a per-wave buffer, loaded
-// at the start of a step and stored at its end, and the trajectory's inputs
-// are reloaded for every segment; nothing floating-point is carried in
-// registers across the divergent refill and finish code.  Every per-wave
-// buffer is laid out [field][lane] (component stride 64), so a wave moves
-// whole 512-byte rows.
+// Between segments a lane keeps only a few integers in registers.  The
+// running cotangents (lambda of y, and of theta) are in registers while a
+// segment is reversed and in a per-wave buffer between segments, and the
+// trajectory's inputs are reloaded for every segment; nothing floating-point
+// is carried in registers across the divergent refill and finish code.
+// Per-wave buffers are laid out [field][lane] (component stride 64), so a
+// wave moves whole 512-byte rows; the stage points of the step being
+// reversed live in LDS.
 // STORE: the tape is in store mode (chosen by the host from ckpt_every), so
 // the kernel holds no replay state at all.
 constexpr int kStoreSegment = 32;
@@ -825,7 +827,10 @@ __global__ void __launch_bounds__(256) vjp_kernel(Params P, VjpParams V) {
   // stretch of the tape (inputs, refill and bookkeeping once per segment).
   const int kseg = store ? kStoreSegment : P.ckpt_every;
   double* scr = V.scratch + (store ? 0 : wave * (int64_t)kseg * SREC * 64 + lane);
-  double* ysc = V.stages + wave * (int64_t)TB::S * D * 64 + lane;
+  // Stage points in dynamic LDS: (s - 1) d doubles per lane of the block.
+  extern __shared__ double gs_lds[];
+  double* ysc = gs_lds + threadIdx.x;
+  const int ys = blockDim.x;
   double* ast = V.adj + wave * (int64_t)R * AREC * 64 + lane;
   auto LAM = [&](int r, int c) -> double& { return ast[(r * AREC + c) * 64]; };
   auto THB = [&](int r, int c) -> double& { return ast[(r * AREC + D + c) * 64]; };
@@ -959,6 +964,16 @@ __global__ void __launch_bounds__(256) vjp_kernel(Params P, VjpParams V) {
     double nx_t = 0.0, nx_h = 0.0, nx_y[D];
     double h_carry = 0.0;  // store mode: h of the step about to be reversed
     bool have = false;
+    // This segment's running cotangents (every lane reads its own slot, so
+    // they are defined on every path).
+    double lam[R][D], thb[R][NP];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+#pragma unroll
+      for (int c = 0; c < D; ++c) lam[r][c] = LAM(r, c);
+#pragma unroll
+      for (int c = 0; c < NP; ++c) thb[r][c] = THB(r, c);
+    }
     for (int jj = kseg - 1; jj >= 0; --jj) {
       const bool act = live && ok && jj < m;
       if (__ballot(act) == 0) continue;
@@ -988,17 +1003,9 @@ __global__ void __launch_bounds__(256) vjp_kernel(Params P, VjpParams V) {
       }
       const bool last_step = cseg * kseg + jj == N - 1;
       const double t_new = last_step ? s.in.t1 : tn + hn;
-      double lam[R][D], thb[R][NP];
-#pragma unroll
-      for (int r = 0; r < R; ++r) {
-#pragma unroll
-        for (int c = 0; c < D; ++c) lam[r][c] = LAM(r, c);
-#pragma unroll
-        for (int c = 0; c < NP; ++c) thb[r][c] = THB(r, c);
-      }
       auto no_seed = [](int, double(&)[TB::S][D], double(&)[D]) {};
       if constexpr (!NODES) {
-        reverse_step<TB, F, R>(s.in, tn, hn, yn, lam, thb, false, no_seed, ysc);
+        reverse_step<TB, F, R>(s.in, tn, hn, yn, lam, thb, false, no_seed, ysc, ys);
       } else {
         // Nodes at the end of the step read y+ itself.
         while (kp >= 0 && node_time(P, kp, idx) == t_new) {
@@ -1038,7 +1045,7 @@ __global__ void __launch_bounds__(256) vjp_kernel(Params P, VjpParams V) {
               for (int c = 0; c < D; ++c) yb[c] += g[c];
             }
           };
-          reverse_step<TB, F, R>(s.in, tn, hn, yn, lam, thb, any, seed, ysc);
+          reverse_step<TB, F, R>(s.in, tn, hn, yn, lam, thb, any, seed, ysc, ys);
           kp = k_lo;
         } else {
           // Shortened-step outputs: each is a full step of length sigma h
@@ -1060,7 +1067,7 @@ __global__ void __launch_bounds__(256) vjp_kernel(Params P, VjpParams V) {
             for (int r = 0; r < R; ++r)
 #pragma unroll
               for (int c = 0; c < D; ++c) lz[r][c] = has ? gbar(r, c, kp) : lam[r][c];
-            reverse_step<TB, F, R>(s.in, tn, hq, yn, lz, thb, false, no_seed, ysc);
+            reverse_step<TB, F, R>(s.in, tn, hq, yn, lz, thb, false, no_seed, ysc, ys);
 #pragma unroll
             for (int r = 0; r < R; ++r)
 #pragma unroll
@@ -1072,6 +1079,9 @@ __global__ void __launch_bounds__(256) vjp_kernel(Params P, VjpParams V) {
           } while (has);
         }
       }
+    }
+    // Segment done.
+    if (live) {
 #pragma unroll
       for (int r = 0; r < R; ++r) {
 #pragma unroll
@@ -1079,9 +1089,6 @@ __global__ void __launch_bounds__(256) vjp_kernel(Params P, VjpParams V) {
 #pragma unroll
         for (int c = 0; c < NP; ++c) THB(r, c) = thb[r][c];
       }
-    }
-    // Segment done.
-    if (live) {
       cseg -= 1;
       if (!ok || cseg < 0) finish();
     }

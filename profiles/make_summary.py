@@ -1,7 +1,8 @@
 """Write short text summaries of rocprofv3 output for profiles/.
 
-  python profiles/make_summary.py trace <results.db> "<command>"
-      kernel-trace statistics (top kernels and per-dispatch durations)
+  python profiles/make_summary.py trace <results.db> "<command>" [name filter]
+      kernel-trace statistics (top kernels and per-dispatch durations),
+      optionally only kernels whose name contains the filter
   python profiles/make_summary.py traffic <fetch.csv> <write.csv> <kernel-sha> "<commands>"
       HBM bytes per solve launch from FETCH_SIZE / WRITE_SIZE passes, each
       scaled by what the same counter reads for a 1 GiB device copy
@@ -13,18 +14,23 @@ import sys
 GIB_KIB = 1 << 20  # FETCH_SIZE / WRITE_SIZE count KiB
 
 
-def trace(db, cmd):
+def trace(db, cmd, only=""):
     c = sqlite3.connect(db)
     print(f"command: `{cmd}`\n")
+    if only:
+        print(f"kernels whose name contains `{only}`\n")
     print("| kernel | calls | total ms | average ms | % |")
     print("|---|---|---|---|---|")
     # top_kernels reports microseconds, the kernels table nanoseconds.
     for name, calls, tot, avg, pct in c.execute(
             "select name, total_calls, total_duration, average, percentage from top_kernels"):
+        if only and only not in name:
+            continue
         print(f"| {name[:90]} | {calls} | {tot / 1e3:.3f} | {avg / 1e3:.4f} | {pct:.2f} |")
     rows = list(c.execute("select name, duration, grid_x, workgroup_x, vgpr_count, "
                           "accum_vgpr_count, scratch_size from kernels order by start"))
-    solve = [r for r in rows if "solve_kernel" in r[0] or "vjp_kernel" in r[0]]
+    solve = [r for r in rows if ("solve_kernel" in r[0] or "vjp_kernel" in r[0])
+             and (not only or only in r[0])]
     if solve:
         print("\nper dispatch (solve/vjp kernels): duration ms, grid, block, vgpr, agpr, scratch")
         for r in solve:
@@ -71,6 +77,6 @@ def traffic(fetch_csv, write_csv, sha, cmds):
 
 if __name__ == "__main__":
     if sys.argv[1] == "trace":
-        trace(sys.argv[2], sys.argv[3])
+        trace(sys.argv[2], sys.argv[3], sys.argv[4] if len(sys.argv) > 4 else "")
     else:
         traffic(sys.argv[2], sys.argv[3], sys.argv[4], sys.argv[5])
