@@ -152,6 +152,12 @@ typedef struct gs_solve_args {
   int32_t grid;          /* workgroups of the persistent grid               */
   int32_t refill;        /* refill a wavefront once this many lanes idle,
                             1..64                                           */
+  int32_t wide;          /* the first `wide` trajectories of the queue order
+                            run on 16 lanes each (one state component per
+                            lane) in the same launch, for the long tail of
+                            uneven ensembles; results are bit-identical to
+                            one lane per trajectory.  0 = none.  Needs the
+                            queue schedule, K = 0 and no tape.              */
   const int64_t* order;  /* [n] queue order (a permutation of 0..n-1), or
                             NULL for 0, 1, ..., n-1                         */
 

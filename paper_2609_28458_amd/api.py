@@ -53,7 +53,7 @@ class gs_solve_args(C.Structure):
         ("max_steps", C.c_int64), ("h0", C.c_double), ("ctrl", gs_controller),
         ("ckpt_every", C.c_int32), ("ckpt_capacity", C.c_int32),
         ("schedule", C.c_int32), ("block", C.c_int32), ("grid", C.c_int32),
-        ("refill", C.c_int32), ("order", C.c_void_p),
+        ("refill", C.c_int32), ("wide", C.c_int32), ("order", C.c_void_p),
         ("workspace", C.c_void_p), ("workspace_bytes", C.c_size_t), ("stream", C.c_void_p),
     ]
 
@@ -239,6 +239,7 @@ class Launch:
     block: int = 0
     grid: int = 0
     refill: int = 0
+    wide: int = 0
     ckpt_every: int = 0
     ckpt_capacity: int = 0
     max_steps: int = 0
@@ -302,7 +303,7 @@ class Solution:
         a.ctrl = gs_controller(L.safety, L.alpha_min, L.alpha_max, L.beta1, L.beta2)
         a.ckpt_every, a.ckpt_capacity = L.ckpt_every, L.ckpt_capacity
         a.schedule = SCHEDULE[L.schedule]
-        a.block, a.grid, a.refill = L.block, L.grid, L.refill
+        a.block, a.grid, a.refill, a.wide = L.block, L.grid, L.refill, L.wide
         return a
 
     def set_order(self, order):

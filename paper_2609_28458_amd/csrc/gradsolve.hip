@@ -32,6 +32,10 @@ constexpr int kVjpMaxR = 1;
 __global__ void reset_counters_kernel(unsigned long long* c, int n) {
   if ((int)threadIdx.x < n) c[threadIdx.x] = 0ull;
 }
+// Forward queue heads: single lanes start after the wide head of the order.
+__global__ void reset_queues_kernel(unsigned long long* c, long long n_wide) {
+  if (threadIdx.x < 4) c[threadIdx.x] = threadIdx.x == 0 ? (unsigned long long)n_wide : 0ull;
+}
 
 int rhs_dim(int r) {
   static const int d[kNumRhs] = {gs::Harmonic::D, gs::Kepler::D, gs::LogHalo::D,
@@ -104,6 +108,9 @@ gs_status check_args(const gs_solve_args* a) {
     return GS_ERR_INVALID;
   if (a->grid < 0) return GS_ERR_INVALID;
   if (a->refill < 0 || a->refill > 64) return GS_ERR_INVALID;
+  if (a->wide < 0) return GS_ERR_INVALID;
+  if (a->wide > 0 && (a->schedule != GS_SCHED_QUEUE || a->K > 0 || a->ckpt_every > 0))
+    return GS_ERR_UNSUPPORTED;
   const gs_controller& c = a->ctrl;
   if (!(c.safety > 0.0) || !(c.alpha_min > 0.0) || !(c.alpha_max >= 1.0) ||
       !(c.alpha_min <= 1.0))
@@ -152,6 +159,8 @@ Params make_params(const gs_solve_args* a) {
   P.order = a->order;
   P.refill = a->refill > 0 ? a->refill : 16;
   P.sched_static = a->schedule == GS_SCHED_STATIC ? 1 : 0;
+  P.n_wide = std::min<int64_t>(a->wide, a->n);
+  P.wide_blocks = 0;  // set with the launch shape
   P.fast_ctrl = (a->ctrl.beta1 <= 0.0 && a->ctrl.beta2 == 0.0 && a->ctrl.alpha_max <= 100.0 &&
                  a->ctrl.alpha_min >= 0.01)
                     ? 1
@@ -222,10 +231,18 @@ void solve_shape(const gs_solve_args* a, int* grid, int* block) {
 gs_status launch_solve_all(const gs_solve_args* a) {
   hipStream_t s = static_cast<hipStream_t>(a->stream);
   const Params P = make_params(a);
-  hipLaunchKernelGGL(reset_counters_kernel, dim3(1), dim3(64), 0, s, P.counters, 4);
+  Params P2 = P;
+  hipLaunchKernelGGL(reset_queues_kernel, dim3(1), dim3(64), 0, s, P.counters, (long long)P.n_wide);
   int grid = 0, block = 0;
   solve_shape(a, &grid, &block);
-  ops(a->rhs, a->tableau).solve(P, grid, block, s);
+  if (P.n_wide > 0) {
+    // One workgroup holds block / 16 groups; all wide trajectories start at
+    // once, ahead of the single-lane workgroups.
+    const int per_block = block / gs::kGroup;
+    P2.wide_blocks = (int)((P.n_wide + per_block - 1) / per_block);
+    grid = std::max(grid - P2.wide_blocks, 1) + P2.wide_blocks;
+  }
+  ops(a->rhs, a->tableau).solve(P2, grid, block, s);
   return hipGetLastError() == hipSuccess ? GS_OK : GS_ERR_HIP;
 }
 

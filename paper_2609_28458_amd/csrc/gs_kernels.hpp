@@ -95,6 +95,8 @@ struct Params {
   int32_t refill;
   int32_t sched_static;
   int32_t fast_ctrl;  // I controller with default exponent and alpha in [0.01, 100]
+  int64_t n_wide;     // queue positions [0, n_wide) run 16 lanes per trajectory
+  int32_t wide_blocks;  // the first wide_blocks workgroups run those
 };
 
 struct VjpParams {
@@ -540,6 +542,248 @@ struct FwdOccupancy {
   static constexpr int waves = (TB::S * F::D > 63) ? 1 : GS_FWD_WAVES;
 };
 
+
+// ---------------------------------------------------------------------------
+// Group mode: one trajectory on a group of 16 lanes (a DPP row), lane c of
+// the group holding component c of the state and of every stage.  Stage
+// sums and error terms are the single-lane expressions for that component;
+// each stage point is broadcast within the row so that every lane evaluates
+// the ordinary right-hand side on the full vector and keeps its component;
+// the norm is a butterfly over the row whose pairing is the pairwise order
+// of error_norm2 (lanes beyond d hold +0, which adds exactly).  A group
+// therefore takes the same steps, bit for bit, as a single lane, with about
+// a sixth of the stage arithmetic on the critical path of one trajectory.
+constexpr int kGroup = 16;
+
+template <int CTRL>
+__device__ __forceinline__ double dpp_mov(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+// Lane SRC of this lane's row, in every lane of the row (row_newbcast).
+template <int SRC>
+__device__ __forceinline__ double row_bcast(double v) {
+  return dpp_mov<0x150 + SRC>(v);
+}
+// Sum over the 16 lanes of the row: partners l^1, l^2 (quad_perm), then the
+// other quad of the half-row (row_half_mirror), then the other half-row
+// (row_mirror); every lane ends with the same value.
+__device__ __forceinline__ double row_sum(double v) {
+  v = v + dpp_mov<0xB1>(v);
+  v = v + dpp_mov<0x4E>(v);
+  v = v + dpp_mov<0x141>(v);
+  v = v + dpp_mov<0x140>(v);
+  return v;
+}
+
+// Full vector of the row's components (lanes 0..D-1), in every lane.
+template <int D>
+__device__ __forceinline__ void row_gather(double v, double (&out)[D]) {
+  sfor<D>([&](auto C) {
+    constexpr int c = decltype(C)::value;
+    out[c] = row_bcast<c>(v);
+  });
+}
+// Component c of a full vector (c is the lane's own index).  Written as
+// bit masks: as a chain of selects the compiler turns it into a store of
+// the vector to scratch and an indexed load.
+template <int D>
+__device__ __forceinline__ double pick(const double (&v)[D], int c) {
+  unsigned long long r = __double_as_longlong(v[0]);
+#pragma unroll
+  for (int j = 1; j < D; ++j) {
+    const unsigned long long m = 0ull - (unsigned long long)(c == j);
+    r = (r & ~m) | ((unsigned long long)__double_as_longlong(v[j]) & m);
+  }
+  return __longlong_as_double((long long)r);
+}
+
+template <class TB, class F>
+struct GroupTraj {
+  static constexpr int S = TB::S, D = F::D;
+  Inputs<F> in;
+  double y;     // own component (0 beyond d)
+  double k[S];  // own component of each stage derivative
+  double t, h, err_prev2;
+  int32_t nacc, nrej, nanrun;
+};
+
+// One attempt of a group: the single-lane attempt() component by component.
+template <class TB, class F>
+__device__ __forceinline__ Attempt group_attempt(const Params& P, GroupTraj<TB, F>& s, int c) {
+  constexpr int S = TB::S, D = F::D;
+  const bool mine = c < D;
+  Attempt a;
+  a.t_start = s.t;
+  bool last = false;
+  double hh = s.h;
+  if (s.t + hh >= s.in.t1) {
+    hh = s.in.t1 - s.t;
+    last = true;
+  }
+  a.h_used = hh;
+  double yn = 0.0;
+  sfor<S - 1>([&](auto J1) {
+    constexpr int j = decltype(J1)::value + 1;
+    double acc = 0.0;
+    sfor<j>([&](auto L) {
+      constexpr int l = decltype(L)::value;
+      constexpr double aj = TB::A(j, l);
+      if constexpr (aj != 0.0) acc = fma(aj, s.k[l], acc);
+    });
+    const double Yc = fma(hh, acc, s.y);
+    double Y[D], kf[D];
+    row_gather<D>(Yc, Y);
+    F::f(s.t + TB::C(j) * hh, Y, s.in.par, kf);
+    s.k[j] = mine ? pick<D>(kf, c) : 0.0;
+    if constexpr (TB::FSAL && j == S - 1) yn = Yc;
+  });
+  if constexpr (!TB::FSAL) {
+    double acc = 0.0;
+    sfor<S>([&](auto J) {
+      constexpr int j = decltype(J)::value;
+      constexpr double b = TB::B(j);
+      if constexpr (b != 0.0) acc = fma(b, s.k[j], acc);
+    });
+    yn = fma(hh, acc, s.y);
+  }
+  double e = 0.0;
+  sfor<S>([&](auto J) {
+    constexpr int j = decltype(J)::value;
+    constexpr double w = TB::E(j);
+    if constexpr (w != 0.0) e = fma(w, s.k[j], e);
+  });
+  e *= hh;
+  const double sc = fma(s.in.rtol, dmax(fabs(s.y), fabs(yn)), s.in.atol);
+  const double r = e * fast_rcp1(sc);
+  const double en2 = row_sum(mine ? r * r : 0.0) * (1.0 / D);
+  const bool finite = (en2 - en2) == 0.0;
+  const double factor = step_factor<TB>(P, en2, s.err_prev2, finite);
+  const bool acc = finite & (en2 <= 1.0);
+  a.accepted = acc;
+  const double t_new = last ? s.in.t1 : s.t + hh;
+  a.t_new = t_new;
+  const bool fin = row_sum(mine ? fma(yn, 0.0, 0.0) : 0.0) == 0.0;
+  s.y = acc ? yn : s.y;
+  s.t = acc ? t_new : s.t;
+  if constexpr (TB::FSAL) {
+    s.k[0] = acc ? s.k[S - 1] : s.k[0];
+  } else {
+    double Y[D], kf[D];
+    row_gather<D>(s.y, Y);
+    F::f(s.t, Y, s.in.par, kf);
+    s.k[0] = mine ? pick<D>(kf, c) : 0.0;
+  }
+  s.err_prev2 = acc ? dmax(en2, 1e-8) : s.err_prev2;
+  s.nacc += acc ? 1 : 0;
+  s.nrej += acc ? 0 : 1;
+  s.nanrun = finite ? 0 : s.nanrun + 1;
+  s.h = hh * factor;
+  const bool bad_state = acc & !fin;
+  const bool nan_fail = !finite & (s.nanrun >= 50);
+  const bool done = acc & last;
+  const bool tiny = !done & underflow(s.h, s.t);
+  a.finished = bad_state | nan_fail | done | tiny;
+  a.status = (bad_state | nan_fail) ? ST_NONFINITE : (tiny ? ST_DT_UNDERFLOW : ST_OK);
+  return a;
+}
+
+// The group part of a forward launch: workgroups [0, wide_blocks) take the
+// queue positions [0, n_wide) (the head of the order, longest first when
+// the caller sorts by predicted cost), one per 16-lane group, from their own
+// queue head (counters[3]).  Control mirrors the single-lane loop; every
+// ballot sits where all lanes of the wave execute it.
+template <class TB, class F>
+__device__ void solve_group(const Params& P) {
+  constexpr int D = F::D;
+  const int lane = threadIdx.x & 63;
+  const int c = lane & (kGroup - 1);
+  const int first = lane & ~(kGroup - 1);  // the group's lane 0
+  GroupTraj<TB, F> s;
+  int64_t idx = -1;
+  bool live = false;
+  bool queue_empty = false;
+
+  auto finish = [&](int32_t st) {
+    if (c < D) P.y_final[(int64_t)c * P.n + idx] = s.y;
+    if (c == 0) {
+      P.n_acc[idx] = s.nacc;
+      P.n_rej[idx] = s.nrej;
+      P.status[idx] = st;
+    }
+    live = false;
+  };
+  auto start = [&](int64_t i) {
+    idx = i;
+    live = true;
+    s.nacc = s.nrej = s.nanrun = 0;
+    s.err_prev2 = 1.0;
+    double y0[D];
+    load_inputs<F>(P, i, s.in, y0);
+    s.t = s.in.t0;
+    s.y = c < D ? pick<D>(y0, c) : 0.0;
+    bool fin = true;
+#pragma unroll
+    for (int j = 0; j < D; ++j) fin = fin && (y0[j] == y0[j]) && (fabs(y0[j]) < __builtin_inf());
+    if (!inputs_valid<F>(P, i, s.in)) {
+      finish(ST_BAD_INPUT);
+      return;
+    }
+    if (!fin) {
+      finish(ST_NONFINITE);
+      return;
+    }
+    if (!(s.in.t1 > s.in.t0)) {
+      finish(ST_OK);
+      return;
+    }
+    double f0[D];
+    F::f(s.t, y0, s.in.par, f0);
+    s.k[0] = c < D ? pick<D>(f0, c) : 0.0;
+    s.h = P.h0 > 0.0 ? dmin(P.h0, s.in.t1 - s.in.t0) : initial_step<TB, F>(s.in, y0, f0);
+  };
+
+  for (;;) {
+    if (!queue_empty) {
+      // one bit per idle group (its lane 0)
+      const uint64_t idle = __ballot(!live && c == 0);
+      const int nidle = __popcll(idle);
+      if (nidle > 0) {
+        unsigned long long base = 0;
+        if (lane == 0) base = atomicAdd(P.counters + 3, (unsigned long long)nidle);
+        base = first_lane(base);
+        if (base + (unsigned long long)nidle >= (unsigned long long)P.n_wide) queue_empty = true;
+        if (!live) {
+          const uint64_t below = first ? (~0ull >> (64 - first)) : 0ull;
+          const unsigned long long pos = base + __popcll(idle & below);
+          if (pos < (unsigned long long)P.n_wide) {
+            const int64_t id = P.order ? P.order[pos] : (int64_t)pos;
+            if (id >= 0 && id < P.n) start(id);
+          }
+        }
+      }
+    }
+    if (__ballot(live) == 0) {
+      if (queue_empty) break;
+      continue;
+    }
+    int32_t st = -1;
+    for (;;) {
+      if (live) {
+        if ((int64_t)s.nacc + s.nrej >= P.max_steps) {
+          st = ST_MAX_STEPS;
+        } else {
+          const Attempt a = group_attempt<TB, F>(P, s, c);
+          if (a.finished) st = a.status;
+        }
+      }
+      if (__ballot(live && st >= 0) != 0) break;
+    }
+    if (live && st >= 0) finish(st);
+  }
+}
+
 // NODES: the call has output nodes (K > 0); TAPE: it keeps a checkpoint
 // tape.  The host picks the variant, so a plain solve runs a loop with
 // neither check in it.
@@ -547,6 +791,12 @@ template <class TB, class F, bool NODES, bool TAPE>
 __global__ void __launch_bounds__(256)
     __attribute__((amdgpu_waves_per_eu(FwdOccupancy<TB, F>::waves, 8))) solve_kernel(Params P) {
   constexpr int D = F::D;
+  if constexpr (!NODES && !TAPE && F::D <= kGroup) {
+    if ((int)blockIdx.x < P.wide_blocks) {  // uniform per workgroup
+      solve_group<TB, F>(P);
+      return;
+    }
+  }
   Traj<TB, F> s;
   int64_t idx = -1;
   int32_t kp = 0;

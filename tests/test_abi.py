@@ -59,7 +59,7 @@ def _args(**kw):
 @pytest.mark.parametrize("kw", [
     dict(rhs=7), dict(tableau=3), dict(d=5), dict(p=4), dict(n=-1),
     dict(y0=None), dict(theta_stride=5), dict(t_stride=2), dict(K=3),
-    dict(ckpt_every=-1), dict(ckpt_every=4, ckpt_capacity=0), dict(block=100),
+    dict(ckpt_every=-1), dict(ckpt_every=4, ckpt_capacity=0), dict(block=100), dict(wide=-1),
     dict(block=1024), dict(refill=65), dict(schedule=5),
 ])
 def test_invalid_arguments_rejected(kw):
@@ -94,3 +94,10 @@ def test_status_strings():
     for code in range(6):
         assert api.lib().gs_status_string(code)
     assert api.gs_version() == "0.1.0"
+
+
+def test_wide_needs_queue_schedule_without_outputs_or_tape():
+    # groups of lanes run the plain forward only
+    for kw in (dict(wide=8, schedule=1), dict(wide=8, ckpt_every=4, ckpt_capacity=10),
+               dict(wide=8, K=3, t_out=0x1000, y_out=0x1000)):
+        assert api.lib().gs_solve(C.byref(_args(**kw))) == 2

@@ -180,3 +180,31 @@ def test_rhs_vjp_matches_oracle_jacobian(orc):
                                        err_msg=f"{name} ybar")
             np.testing.assert_allclose(tb[:, i], vj[d:], rtol=0, atol=1e-12 * scale,
                                        err_msg=f"{name} thetabar")
+
+
+@pytest.mark.parametrize("tab", ["dopri5", "tsit5", "verner7"])
+@pytest.mark.parametrize("name,make", CASES, ids=[c[0] for c in CASES])
+def test_wide_groups_are_bitwise_identical(name, make, tab):
+    """Trajectories run on 16-lane groups (one component per lane) take the
+    same steps and give the same bits as on one lane, for every right-hand
+    side and tableau; some of the ensemble on groups, or all of it."""
+    w = {**make(333), "tableau": tab, "t_out": None}
+    ref = to_np(gpu_solve(w))
+    assert np.all(ref["status"] == 0)
+    for wide in (37, 333):
+        g = to_np(gpu_solve(w, api.Launch(wide=wide)))
+        for k in ref:
+            np.testing.assert_array_equal(g[k], ref[k], err_msg=f"{k} wide={wide}")
+
+
+def test_wide_groups_on_the_uneven_batch(orc):
+    """Longest-first order with the 300 predicted-longest orbits of 20,000 on
+    groups: bitwise equal to one lane each, and to the oracle on a sample."""
+    w = inputs.orbits_uneven(n=20_000, seed=47)
+    order = np.argsort(-inputs.predicted_cost(w), kind="stable")
+    ref = to_np(gpu_solve(w, order=order))
+    g = to_np(gpu_solve(w, api.Launch(wide=300, block=128), order=order))
+    for k in ref:
+        np.testing.assert_array_equal(g[k], ref[k])
+    idx = np.sort(np.concatenate([order[:60], order[-40:]]))
+    _check(g, oracle_solve(orc, w, idx), idx)
