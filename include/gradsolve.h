@@ -214,6 +214,25 @@ gs_status gs_solve(const gs_solve_args* args);
  * Trajectories whose status is not GS_TRAJ_OK get NaN cotangents. */
 gs_status gs_solve_vjp(const gs_solve_args* fwd, const gs_vjp_args* vjp);
 
+/* Forward sensitivities for a gs_solve (eq:sens carried through the
+ * stages, eq:stage-sens): M columns, each the derivative of the solution with
+ * respect to one input, cols[m] < d for the initial condition y0[cols[m]] or
+ * d <= cols[m] < d + p for the parameter theta[cols[m] - d].  In the same
+ * launch as the solution (which is written exactly as gs_solve writes it,
+ * with the same steps, since step control reads the values only).  Outputs
+ * S_final [d][M][n] and, when K > 0, S_out [d][M][K][n]: S[c][m] is
+ * d y_c / d input_m; for shared theta (theta_stride 0) it is the derivative
+ * of each trajectory with respect to the shared value.  Columns run two per
+ * launch.  No tape, no wide groups, queue schedule only.  1 <= M <= 16. */
+typedef struct gs_sens_args {
+  int32_t M;
+  const int32_t* cols;    /* [M], host memory                              */
+  double* S_final;        /* [d][M][n]                                     */
+  double* S_out;          /* [d][M][K][n], or NULL when K = 0              */
+} gs_sens_args;
+
+gs_status gs_solve_sens(const gs_solve_args* args, const gs_sens_args* sens);
+
 /* Solution at arbitrary times t_query [Q][n] (each in [t0, t1]) from the tape
  * of the last gs_solve with `fwd` (eq:dense; replay from the nearest
  * checkpoint, or from t0 when no tape was kept).  y_query is [d][Q][n]. */

@@ -66,7 +66,14 @@ class gs_vjp_args(C.Structure):
     ]
 
 
-EXPORTS = ["gs_default_args", "gs_workspace_bytes", "gs_solve", "gs_solve_vjp", "gs_dense_eval",
+class gs_sens_args(C.Structure):
+    _fields_ = [
+        ("M", C.c_int32), ("cols", C.c_void_p), ("S_final", C.c_void_p), ("S_out", C.c_void_p),
+    ]
+
+
+EXPORTS = ["gs_default_args", "gs_workspace_bytes", "gs_solve", "gs_solve_vjp", "gs_solve_sens",
+           "gs_dense_eval",
            "gs_rhs_eval", "gs_graph_create", "gs_graph_launch", "gs_graph_destroy",
            "gs_status_string", "gs_version"]
 
@@ -89,6 +96,8 @@ def lib():
         L.gs_solve.restype = C.c_int
         L.gs_solve_vjp.argtypes = [C.POINTER(gs_solve_args), C.POINTER(gs_vjp_args)]
         L.gs_solve_vjp.restype = C.c_int
+        L.gs_solve_sens.argtypes = [C.POINTER(gs_solve_args), C.POINTER(gs_sens_args)]
+        L.gs_solve_sens.restype = C.c_int
         L.gs_dense_eval.argtypes = [C.POINTER(gs_solve_args), C.c_int32, C.c_void_p, C.c_void_p,
                                     C.c_void_p]
         L.gs_dense_eval.restype = C.c_int
@@ -325,6 +334,28 @@ def solve(prob: Problem, launch: Launch | None = None, order=None, stream=None) 
     if order is not None:
         sol.set_order(order)
     return sol.run(stream)
+
+
+def gs_solve_sens(args: gs_solve_args, sens: gs_sens_args) -> None:
+    _check(lib().gs_solve_sens(C.byref(args), C.byref(sens)))
+
+
+def solve_sens(prob: Problem, cols, launch: Launch | None = None, stream=None):
+    """Solution plus forward sensitivities (eq:sens) of the columns ``cols``:
+    index c < d is y0[c], d + q is theta[q].  Returns (Solution, S_final
+    [d][M][n], S_out [d][M][K][n] or None)."""
+    sol = Solution(prob, launch or Launch())
+    cols = [int(c) for c in cols]
+    M = len(cols)
+    dev = prob.y0.device
+    S_final = torch.empty((prob.d, M, prob.n), dtype=torch.float64, device=dev)
+    S_out = (torch.empty((prob.d, M, prob.K, prob.n), dtype=torch.float64, device=dev)
+             if prob.K else None)
+    ccols = (C.c_int32 * M)(*cols)
+    s = gs_sens_args(M, C.cast(ccols, C.c_void_p), _ptr(S_final), _ptr(S_out))
+    sol.args.stream = _stream_handle(stream)
+    gs_solve_sens(sol.args, s)
+    return sol, S_final, S_out
 
 
 def solve_vjp(sol: Solution, ybar_final=None, ybar_out=None, block=0, grid=0, stream=None):

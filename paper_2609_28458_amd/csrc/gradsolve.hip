@@ -26,6 +26,7 @@ constexpr size_t kCounterBytes = 256;
 // per lane keeps the adjoint kernels small enough to compile without
 // kilobytes of register spills for the largest right-hand sides.
 constexpr int kVjpMaxR = 1;
+constexpr int kSensMaxCols = 16;          // sensitivity columns per call
 
 // Clears the queue and replay counters at the head of the workspace (a
 // kernel rather than a memset, so a captured graph holds no memset node).
@@ -329,6 +330,44 @@ gs_status gs_solve_vjp(const gs_solve_args* fwd, const gs_vjp_args* v) {
     V.R = std::min(kVjpMaxR, v->R - r0);
     hipLaunchKernelGGL(reset_counters_kernel, dim3(1), dim3(64), 0, s, P.counters + 1, 1);
     ops(fwd->rhs, fwd->tableau).vjp(P, V, grid, block, s);
+  }
+  return hipGetLastError() == hipSuccess ? GS_OK : GS_ERR_HIP;
+}
+
+gs_status gs_solve_sens(const gs_solve_args* a, const gs_sens_args* sa) {
+  gs_status st = check_args(a);
+  if (st != GS_OK) return st;
+  if (!sa || sa->M < 1 || sa->M > kSensMaxCols || !sa->cols || !sa->S_final) return GS_ERR_INVALID;
+  if (a->K > 0 && !sa->S_out) return GS_ERR_INVALID;
+  if (a->ckpt_every > 0 || a->wide > 0 || a->schedule != GS_SCHED_QUEUE) return GS_ERR_UNSUPPORTED;
+  for (int m = 0; m < sa->M; ++m)
+    if (sa->cols[m] < 0 || sa->cols[m] >= a->d + a->p) return GS_ERR_INVALID;
+  if (a->n == 0) return GS_OK;
+  hipStream_t s = static_cast<hipStream_t>(a->stream);
+  const Params P = make_params(a);
+  const int block = a->block > 0 ? a->block : 256;
+  gs::SensParams S;
+  std::memset(&S, 0, sizeof S);
+  S.m_total = sa->M;
+  S.S_final = sa->S_final;
+  S.S_out = sa->S_out;
+  // Two columns per launch; each launch integrates the solution again and
+  // rewrites the same values.
+  for (int m0 = 0; m0 < sa->M; m0 += 2) {
+    const int mm = std::min(2, sa->M - m0);
+    S.m0 = m0;
+    for (int m = 0; m < 4; ++m) S.col[m] = m < mm ? sa->cols[m0 + m] : -1;
+    const int64_t need = (a->n + block - 1) / block;
+    int grid = a->grid > 0 ? (int)std::min<int64_t>(a->grid, need) : 0;
+    if (grid == 0) {
+      int per_cu = 0;
+      S.occupancy_out = &per_cu;
+      ops(a->rhs, a->tableau).sens(P, S, mm, 0, block, s);
+      S.occupancy_out = nullptr;
+      grid = (int)std::min<int64_t>((int64_t)std::max(per_cu, 1) * num_cus(), need);
+    }
+    hipLaunchKernelGGL(reset_queues_kernel, dim3(1), dim3(64), 0, s, P.counters, 0ll);
+    ops(a->rhs, a->tableau).sens(P, S, mm, grid, block, s);
   }
   return hipGetLastError() == hipSuccess ? GS_OK : GS_ERR_HIP;
 }

@@ -60,10 +60,36 @@ void launch_dense(const gs::Params& P, int32_t Q, const double* tq, double* yq, 
   hipLaunchKernelGGL((gs::dense_kernel<TB, F>), dim3(grid), dim3(block), 0, s, P, Q, tq, yq);
 }
 
+template <class TB, class F, int M>
+void launch_sens_m(const gs::Params& P, const gs::SensParams& S, int grid, int block,
+                   hipStream_t s) {
+  const void* fn = P.K > 0 ? reinterpret_cast<const void*>(&gs::sens_kernel<TB, F, M, true>)
+                           : reinterpret_cast<const void*>(&gs::sens_kernel<TB, F, M, false>);
+  if (grid <= 0) {
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, block, 0) != hipSuccess) per_cu = 0;
+    *S.occupancy_out = per_cu;
+    return;
+  }
+  if (P.K > 0)
+    hipLaunchKernelGGL((gs::sens_kernel<TB, F, M, true>), dim3(grid), dim3(block), 0, s, P, S);
+  else
+    hipLaunchKernelGGL((gs::sens_kernel<TB, F, M, false>), dim3(grid), dim3(block), 0, s, P, S);
+}
+
+template <class TB, class F>
+void launch_sens(const gs::Params& P, const gs::SensParams& S, int M, int grid, int block,
+                 hipStream_t s) {
+  if (M >= 2)
+    launch_sens_m<TB, F, 2>(P, S, grid, block, s);
+  else
+    launch_sens_m<TB, F, 1>(P, S, grid, block, s);
+}
+
 template <class TB, class F>
 Ops make_ops() {
   return Ops{reinterpret_cast<const void*>(&gs::solve_kernel<TB, F, true, true>),
-             &launch_solve<TB, F>, &launch_vjp<TB, F>, &launch_dense<TB, F>};
+             &launch_solve<TB, F>, &launch_vjp<TB, F>, &launch_dense<TB, F>, &launch_sens<TB, F>};
 }
 
 template <class F>

@@ -60,6 +60,25 @@ __device__ __forceinline__ void rfor(Fn&& fn) {
 __device__ __forceinline__ double dmin(double a, double b) { return (b < a) ? b : a; }
 __device__ __forceinline__ double dmax(double a, double b) { return (a < b) ? b : a; }
 
+// Every component of x (value and tangents) set to v.
+__device__ __forceinline__ void set_all(double& x, double v) { x = v; }
+template <int M>
+__device__ __forceinline__ void set_all(ad::Dual<M>& x, double v) {
+  x.v = v;
+#pragma unroll
+  for (int m = 0; m < M; ++m) x.d[m] = v;
+}
+
+// Zero of the solve's scalar type.
+template <class T>
+__device__ __forceinline__ T zero() {
+  if constexpr (std::is_same<T, double>::value) {
+    return 0.0;
+  } else {
+    return ad::constant<ad::width<T>::value>(0.0);
+  }
+}
+
 constexpr int ST_OK = 0, ST_MAX_STEPS = 1, ST_DT_UNDERFLOW = 2, ST_NONFINITE = 3,
               ST_TAPE_OVERFLOW = 4, ST_BAD_INPUT = 5;
 
@@ -118,11 +137,12 @@ __device__ __forceinline__ double node_time(const Params& P, int kk, int64_t i) 
   return P.t_out_stride ? P.t_out[(int64_t)kk * P.t_out_stride + i] : P.t_out[kk];
 }
 
-// Per-trajectory inputs.
-template <class F>
+// Per-trajectory inputs (theta and the constants derived from it in the
+// scalar type of the solve: double, or ad::Dual for sensitivities).
+template <class F, class T = double>
 struct Inputs {
-  double th[F::P];
-  typename F::Par par;
+  T th[F::P];
+  typename F::template ParT<T> par;
   double t0, t1, rtol, atol;
 };
 
@@ -142,8 +162,8 @@ __device__ __forceinline__ void load_inputs(const Params& P, int64_t i, Inputs<F
 }
 
 // Checks that cannot be done on the host without reading device memory.
-template <class F>
-__device__ __forceinline__ bool inputs_valid(const Params& P, int64_t i, const Inputs<F>& in) {
+template <class F, class IN>
+__device__ __forceinline__ bool inputs_valid(const Params& P, int64_t i, const IN& in) {
   bool ok = (in.t1 >= in.t0) && (in.rtol > 0.0) && (in.atol >= 0.0);
   double prev = in.t0;
   for (int kk = 0; kk < P.K; ++kk) {
@@ -164,17 +184,17 @@ __device__ double initial_step(const Inputs<F>& in, const double (&y)[F::D],
 // Stages 2..s of one step of length h from (t, y) with k[0] = f(t, y)
 // given (eq:rk).  Returns y+ in yn.  For FSAL pairs the last stage point is
 // y+ itself (its row of A is b), so yn costs nothing extra.
-template <class TB, class F>
-__device__ __forceinline__ void rk_stages(const typename F::Par& par, double t, double h,
-                                          const double (&y)[F::D], double (&k)[TB::S][F::D],
-                                          double (&yn)[F::D]) {
+template <class TB, class F, class T>
+__device__ __forceinline__ void rk_stages(const typename F::template ParT<T>& par, double t,
+                                          double h, const T (&y)[F::D], T (&k)[TB::S][F::D],
+                                          T (&yn)[F::D]) {
   constexpr int S = TB::S, D = F::D;
   sfor<S - 1>([&](auto J1) {
     constexpr int j = decltype(J1)::value + 1;
-    double Y[D];
+    T Y[D];
 #pragma unroll
     for (int c = 0; c < D; ++c) {
-      double acc = 0.0;
+      T acc = zero<T>();
       sfor<j>([&](auto L) {
         constexpr int l = decltype(L)::value;
         constexpr double a = TB::A(j, l);
@@ -191,7 +211,7 @@ __device__ __forceinline__ void rk_stages(const typename F::Par& par, double t, 
   if constexpr (!TB::FSAL) {
 #pragma unroll
     for (int c = 0; c < D; ++c) {
-      double acc = 0.0;
+      T acc = zero<T>();
       sfor<S>([&](auto J) {
         constexpr int j = decltype(J)::value;
         constexpr double b = TB::B(j);
@@ -205,10 +225,9 @@ __device__ __forceinline__ void rk_stages(const typename F::Par& par, double t, 
 // Square of the scaled RMS norm of eq:errnorm, for e = h sum_j (b_j -
 // bhat_j) k_j.  The square suffices: accept iff it is <= 1, and the
 // controller takes its power directly, so no square root is needed.
-template <class TB, class F>
-__device__ __forceinline__ double error_norm2(double h, const double (&y)[F::D],
-                                              const double (&yn)[F::D],
-                                              const double (&k)[TB::S][F::D], double rtol,
+template <class TB, class F, class T>
+__device__ __forceinline__ double error_norm2(double h, const T (&y)[F::D], const T (&yn)[F::D],
+                                              const T (&k)[TB::S][F::D], double rtol,
                                               double atol) {
   constexpr int D = F::D;
   double sq[D];
@@ -218,10 +237,10 @@ __device__ __forceinline__ double error_norm2(double h, const double (&y)[F::D],
     sfor<TB::S>([&](auto J) {
       constexpr int j = decltype(J)::value;
       constexpr double w = TB::E(j);
-      if constexpr (w != 0.0) e = fma(w, k[j][c], e);
+      if constexpr (w != 0.0) e = fma(w, ad::val(k[j][c]), e);
     });
     e *= h;
-    const double sc = fma(rtol, dmax(fabs(y[c]), fabs(yn[c])), atol);
+    const double sc = fma(rtol, dmax(fabs(ad::val(y[c])), fabs(ad::val(yn[c]))), atol);
     const double r = e * fast_rcp1(sc);
     sq[c] = r * r;
   }
@@ -306,12 +325,11 @@ __device__ double initial_step(const Inputs<F>& in, const double (&y)[F::D],
 // step, y + h sum_j b_j(sigma) k_j = y+ - h sum_j (b_j - b_j(sigma)) k_j, so the
 // start state need not stay live; Verner 7 takes a shortened step of length
 // sigma h from (t, y_start) reusing k[0] = f(t, y_start).
-template <class TB, class F>
-__device__ __forceinline__ void dense_value(const typename F::Par& par, double t, double h,
-                                            double sigma, const double (&y_end)[F::D],
-                                            const double (&y_start)[F::D],
-                                            const double (&k)[TB::S][F::D],
-                                            double (&out)[F::D]) {
+template <class TB, class F, class T>
+__device__ __forceinline__ void dense_value(const typename F::template ParT<T>& par, double t,
+                                            double h, double sigma, const T (&y_end)[F::D],
+                                            const T (&y_start)[F::D], const T (&k)[TB::S][F::D],
+                                            T (&out)[F::D]) {
   constexpr int S = TB::S, D = F::D;
   if constexpr (TB::POLY_DENSE) {
     double w[S];
@@ -326,13 +344,13 @@ __device__ __forceinline__ void dense_value(const typename F::Par& par, double t
     });
 #pragma unroll
     for (int c = 0; c < D; ++c) {
-      double acc = 0.0;
+      T acc = zero<T>();
 #pragma unroll
       for (int j = 0; j < S; ++j) acc = fma(w[j], k[j][c], acc);
       out[c] = fma(-h, acc, y_end[c]);
     }
   } else {
-    double ks[S][D];
+    T ks[S][D];
 #pragma unroll
     for (int c = 0; c < D; ++c) ks[0][c] = k[0][c];
     rk_stages<TB, F>(par, t, sigma * h, y_start, ks, out);
@@ -370,12 +388,12 @@ __device__ __forceinline__ bool underflow(double h, double t) {
 }
 
 // Integration state of one lane.
-template <class TB, class F>
+template <class TB, class F, class T = double>
 struct Traj {
   static constexpr int S = TB::S, D = F::D;
-  Inputs<F> in;
-  double y[D];
-  double k[S][D];
+  Inputs<F, T> in;
+  T y[D];
+  T k[S][D];
   double t, h;
   double err_prev2;  // squared norm of the last accepted step (PI control)
   int32_t nacc, nrej, nanrun;
@@ -396,8 +414,8 @@ struct Attempt {
 // `on_accept(s, t_start, h, y_start)` sees y = y+, t = t_new and the step's
 // stages k (k[0] still f(t_start, y_start)); y_start is only meaningful for
 // shortened-step pairs.
-template <class TB, class F, class OnAccept>
-__device__ __forceinline__ Attempt attempt(const Params& P, Traj<TB, F>& s,
+template <class TB, class F, class T, class OnAccept>
+__device__ __forceinline__ Attempt attempt(const Params& P, Traj<TB, F, T>& s,
                                            OnAccept&& on_accept) {
   constexpr int S = TB::S, D = F::D;
   Attempt a;
@@ -409,7 +427,7 @@ __device__ __forceinline__ Attempt attempt(const Params& P, Traj<TB, F>& s,
     last = true;
   }
   a.h_used = hh;
-  double yn[D];
+  T yn[D];
   rk_stages<TB, F>(s.in.par, s.t, hh, s.y, s.k, yn);
   const double en2 = error_norm2<TB, F>(hh, s.y, yn, s.k, s.in.rtol, s.in.atol);
   // x - x == 0 exactly when x is finite; no short-circuit branches.
@@ -419,13 +437,13 @@ __device__ __forceinline__ Attempt attempt(const Params& P, Traj<TB, F>& s,
   a.accepted = acc;
   const double t_new = last ? s.in.t1 : s.t + hh;
   a.t_new = t_new;
-  double ystart[D];
+  T ystart[D];
   double probe = 0.0;  // becomes NaN if any component of y+ is not finite
 #pragma unroll
   for (int c = 0; c < D; ++c) {
     if constexpr (!TB::POLY_DENSE) ystart[c] = s.y[c];
-    probe = fma(yn[c], 0.0, probe);
-    s.y[c] = acc ? yn[c] : s.y[c];
+    probe = fma(ad::val(yn[c]), 0.0, probe);
+    s.y[c] = ad::select(acc, yn[c], s.y[c]);
   }
   const bool fin = probe == 0.0;
   s.t = acc ? t_new : s.t;
@@ -438,7 +456,7 @@ __device__ __forceinline__ Attempt attempt(const Params& P, Traj<TB, F>& s,
   }
   if constexpr (TB::FSAL) {
 #pragma unroll
-    for (int c = 0; c < D; ++c) s.k[0][c] = acc ? s.k[S - 1][c] : s.k[0][c];
+    for (int c = 0; c < D; ++c) s.k[0][c] = ad::select(acc, s.k[S - 1][c], s.k[0][c]);
   } else {
     // A rejected lane recomputes f at its unchanged (t, y): the same value.
     F::f(s.t, s.y, s.in.par, s.k[0]);
@@ -787,32 +805,97 @@ __device__ void solve_group(const Params& P) {
 // NODES: the call has output nodes (K > 0); TAPE: it keeps a checkpoint
 // tape.  The host picks the variant, so a plain solve runs a loop with
 // neither check in it.
-template <class TB, class F, bool NODES, bool TAPE>
-__global__ void __launch_bounds__(256)
-    __attribute__((amdgpu_waves_per_eu(FwdOccupancy<TB, F>::waves, 8))) solve_kernel(Params P) {
-  constexpr int D = F::D;
-  if constexpr (!NODES && !TAPE && F::D <= kGroup) {
-    if ((int)blockIdx.x < P.wide_blocks) {  // uniform per workgroup
-      solve_group<TB, F>(P);
-      return;
-    }
+// Sensitivity columns of a forward-mode solve (eq:sens, eq:stage-sens):
+// column m seeds the initial-condition component col[m] (< d) or the
+// parameter col[m] - d; tangents of every output land in S_final
+// [d][M][n] and S_out [d][M][K][n].  Step control reads values only, so the
+// steps are those of the plain solve.
+struct SensParams {
+  int32_t col[4];      // this launch's columns (template M of them)
+  int32_t m_total;     // columns of the output arrays
+  int32_t m0;          // first output column of this launch
+  double* S_final;
+  double* S_out;
+  int* occupancy_out;  // host-side, for the launcher's occupancy query only
+};
+
+// Seeded dual inputs: column m is the derivative with respect to
+// y0[col[m]] (col[m] < d) or theta[col[m] - d]; par is prepared from the
+// seeded theta so it carries d par / d theta.
+template <class F, int M>
+__device__ __forceinline__ void seed_inputs(const SensParams& SP, const Inputs<F>& ind,
+                                            const double (&y0)[F::D], Inputs<F, ad::Dual<M>>& in,
+                                            ad::Dual<M> (&y)[F::D]) {
+#pragma unroll
+  for (int c = 0; c < F::D; ++c) {
+    y[c].v = y0[c];
+#pragma unroll
+    for (int m = 0; m < M; ++m) y[c].d[m] = SP.col[m] == c ? 1.0 : 0.0;
   }
-  Traj<TB, F> s;
+#pragma unroll
+  for (int q = 0; q < F::P; ++q) {
+    in.th[q].v = ind.th[q];
+#pragma unroll
+    for (int m = 0; m < M; ++m) in.th[q].d[m] = SP.col[m] == F::D + q ? 1.0 : 0.0;
+  }
+  in.par = F::prep(in.th);
+  in.t0 = ind.t0;
+  in.t1 = ind.t1;
+  in.rtol = ind.rtol;
+  in.atol = ind.atol;
+}
+
+// The forward solve for scalar type T (double, or ad::Dual<M> carrying M
+// sensitivity columns).  Persistent grid: each lane holds one trajectory;
+// when at least `refill` lanes of a wavefront are idle, one atomic fetches
+// that many queue positions and the idle lanes take them (ballot + prefix
+// count).  In static mode lane g integrates trajectory g and is never
+// refilled.
+template <class TB, class F, class T, bool NODES, bool TAPE>
+__device__ __forceinline__ void forward_body(const Params& P, const SensParams& SP) {
+  constexpr int D = F::D;
+  constexpr bool SENS = !std::is_same<T, double>::value;
+  constexpr int M = ad::width<T>::value;
+  static_assert(!(SENS && TAPE), "sensitivity solves keep no tape");
+  Traj<TB, F, T> s;
   int64_t idx = -1;
   int32_t kp = 0;
   bool live = false, overflow = false;
   bool queue_empty = P.sched_static != 0;  // wave-uniform
   const int lane = threadIdx.x & 63;
 
+  // Output node kk of the lane's trajectory: values, and tangents.
+  auto put_node = [&](int kk, const T (&v)[D]) {
+#pragma unroll
+    for (int c = 0; c < D; ++c) {
+      P.y_out[((int64_t)c * P.K + kk) * P.n + idx] = ad::val(v[c]);
+      if constexpr (SENS) {
+#pragma unroll
+        for (int m = 0; m < M; ++m)
+          SP.S_out[(((int64_t)c * SP.m_total + SP.m0 + m) * P.K + kk) * P.n + idx] = v[c].d[m];
+      }
+    }
+  };
   // Write the final results of the lane's trajectory and free the lane.
   auto finish = [&](int32_t st) {
     for (; NODES && kp < P.K; ++kp) {
+      T nan_v[D];
 #pragma unroll
-      for (int c = 0; c < D; ++c)
-        P.y_out[((int64_t)c * P.K + kp) * P.n + idx] = __builtin_nan("");
+      for (int c = 0; c < D; ++c) {
+        nan_v[c] = zero<T>();
+        set_all(nan_v[c], __builtin_nan(""));
+      }
+      put_node(kp, nan_v);
     }
 #pragma unroll
-    for (int c = 0; c < D; ++c) P.y_final[(int64_t)c * P.n + idx] = s.y[c];
+    for (int c = 0; c < D; ++c) {
+      P.y_final[(int64_t)c * P.n + idx] = ad::val(s.y[c]);
+      if constexpr (SENS) {
+#pragma unroll
+        for (int m = 0; m < M; ++m)
+          SP.S_final[((int64_t)c * SP.m_total + SP.m0 + m) * P.n + idx] = s.y[c].d[m];
+      }
+    }
     P.n_acc[idx] = s.nacc;
     P.n_rej[idx] = s.nrej;
     P.status[idx] = (st == ST_OK && overflow) ? ST_TAPE_OVERFLOW : st;
@@ -827,19 +910,27 @@ __global__ void __launch_bounds__(256)
     overflow = false;
     s.nacc = s.nrej = s.nanrun = 0;
     s.err_prev2 = 1.0;
-    load_inputs<F>(P, i, s.in, s.y);
+    Inputs<F> ind;  // the double inputs (the starting-step rule reads values)
+    double y0[D];
+    load_inputs<F>(P, i, ind, y0);
+    if constexpr (SENS) {
+      seed_inputs<F, M>(SP, ind, y0, s.in, s.y);
+    } else {
+      s.in = ind;
+#pragma unroll
+      for (int c = 0; c < D; ++c) s.y[c] = y0[c];
+    }
     s.t = s.in.t0;
     bool fin = true;
 #pragma unroll
-    for (int c = 0; c < D; ++c) fin = fin && (s.y[c] == s.y[c]) && (fabs(s.y[c]) < __builtin_inf());
+    for (int c = 0; c < D; ++c) fin = fin && (y0[c] == y0[c]) && (fabs(y0[c]) < __builtin_inf());
     if (!inputs_valid<F>(P, i, s.in)) {
       finish(ST_BAD_INPUT);
       return;
     }
     // Nodes at t0 take y0.
     while (NODES && kp < P.K && node_time(P, kp, i) <= s.in.t0) {
-#pragma unroll
-      for (int c = 0; c < D; ++c) P.y_out[((int64_t)c * P.K + kp) * P.n + i] = s.y[c];
+      put_node(kp, s.y);
       ++kp;
     }
     if (!fin) {
@@ -851,9 +942,16 @@ __global__ void __launch_bounds__(256)
       return;
     }
     F::f(s.t, s.y, s.in.par, s.k[0]);
-    s.h = P.h0 > 0.0 ? dmin(P.h0, s.in.t1 - s.in.t0) : initial_step<TB, F>(s.in, s.y, s.k[0]);
+    if (P.h0 > 0.0) {
+      s.h = dmin(P.h0, s.in.t1 - s.in.t0);
+    } else {
+      double f0[D];
+#pragma unroll
+      for (int c = 0; c < D; ++c) f0[c] = ad::val(s.k[0][c]);
+      s.h = initial_step<TB, F>(ind, y0, f0);
+    }
     s.ck_left = P.ckpt_every;
-    if (TAPE) {
+    if constexpr (TAPE) {
       if (P.ckpt_cap <= 0)
         overflow = true;
       else if (P.store)
@@ -900,26 +998,24 @@ __global__ void __launch_bounds__(256)
           st = ST_MAX_STEPS;
         } else {
           const Attempt a = attempt<TB, F>(
-              P, s, [&](const Traj<TB, F>& sa, double t_old, double hh, const double (&ys)[D]) {
+              P, s, [&](const Traj<TB, F, T>& sa, double t_old, double hh, const T (&ys)[D]) {
                 if constexpr (!NODES) return;
                 while (kp < P.K) {
                   const double tq = node_time(P, kp, idx);
                   if (!(tq <= sa.t)) break;
-                  double out[D];
                   if (tq == sa.t) {
-#pragma unroll
-                    for (int c = 0; c < D; ++c) out[c] = sa.y[c];
+                    put_node(kp, sa.y);
                   } else {
+                    T out[D];
                     dense_value<TB, F>(sa.in.par, t_old, hh, (tq - t_old) / hh, sa.y, ys, sa.k,
                                        out);
+                    put_node(kp, out);
                   }
-#pragma unroll
-                  for (int c = 0; c < D; ++c)
-                    P.y_out[((int64_t)c * P.K + kp) * P.n + idx] = out[c];
                   ++kp;
                 }
               });
-          if (TAPE && P.store) {
+          if constexpr (!TAPE) {
+          } else if (P.store) {
             // Every accepted step, the last one included.
             if (a.accepted) {
               if (s.nacc < P.ckpt_cap)
@@ -927,7 +1023,7 @@ __global__ void __launch_bounds__(256)
               else
                 overflow = true;
             }
-          } else if (TAPE && !a.finished) {
+          } else if (!a.finished) {
             s.ck_left -= a.accepted ? 1 : 0;
             if (s.ck_left == 0) {
               s.ck_left = P.ckpt_every;
@@ -945,6 +1041,27 @@ __global__ void __launch_bounds__(256)
     }
     if (live && st >= 0) finish(st);
   }
+}
+
+
+// Plain forward solve (and, with wide > 0, the head of the queue on 16-lane
+// groups).
+template <class TB, class F, bool NODES, bool TAPE>
+__global__ void __launch_bounds__(256)
+    __attribute__((amdgpu_waves_per_eu(FwdOccupancy<TB, F>::waves, 8))) solve_kernel(Params P) {
+  if constexpr (!NODES && !TAPE && F::D <= kGroup) {
+    if ((int)blockIdx.x < P.wide_blocks) {  // uniform per workgroup
+      solve_group<TB, F>(P);
+      return;
+    }
+  }
+  forward_body<TB, F, double, NODES, TAPE>(P, SensParams{});
+}
+
+// Forward solve with M sensitivity columns in the same launch.
+template <class TB, class F, int M, bool NODES>
+__global__ void __launch_bounds__(256) sens_kernel(Params P, SensParams SP) {
+  forward_body<TB, F, ad::Dual<M>, NODES, false>(P, SP);
 }
 
 // ---------------------------------------------------------------------------

@@ -18,6 +18,9 @@ struct Ops {
   void (*vjp)(const gs::Params&, const gs::VjpParams&, int grid, int block, hipStream_t);
   void (*dense)(const gs::Params&, int32_t Q, const double*, double*, int grid, int block,
                 hipStream_t);
+  // Sensitivity solve with M (1 or 2) columns; grid <= 0 writes the blocks
+  // per CU of the variant to *S.occupancy_out instead of launching.
+  void (*sens)(const gs::Params&, const gs::SensParams&, int M, int grid, int block, hipStream_t);
 };
 
 // Fill row[GS_DOPRI5], row[GS_TSIT5], row[GS_VERNER7] for one right-hand side.

@@ -6,12 +6,16 @@
 //   Par prep(theta)      per-trajectory constants derived from theta (done
 //                        once per trajectory, kept in registers)
 //   f(t, y, par, dy)     the right-hand side
+// prep and f are templates on the scalar type: double, or the forward-mode
+// ad::Dual of the sensitivity kernels (ParT<Dual> carries d par / d theta).
 //   vjp(t, y, theta, par, kb, yb, thb)
 //                        yb = J_y^T kb (overwritten), thb += J_theta^T kb
 // All loops have compile-time trip counts so arrays stay in VGPRs.
 #pragma once
 
 #include <hip/hip_runtime.h>
+
+#include "gs_dual.hpp"
 
 namespace gs {
 
@@ -33,13 +37,30 @@ __device__ __forceinline__ double fast_rcp1(double x) {
   return fma(r, fma(-x, r, 1.0), r);
 }
 
+namespace ad {
+// d(1/x) = -x' / x^2, with the value of the double version.
+template <int M>
+__device__ __forceinline__ Dual<M> fast_rcp(const Dual<M>& x) {
+  Dual<M> r;
+  r.v = gs::fast_rcp(x.v);
+  const double g = -r.v * r.v;
+#pragma unroll
+  for (int m = 0; m < M; ++m) r.d[m] = g * x.d[m];
+  return r;
+}
+}  // namespace ad
+
 // ---------------------------------------------------------------------------
 // Harmonic oscillator: x' = v, v' = -omega^2 x.  Closed-form test system.
 struct Harmonic {
   static constexpr int D = 2, P = 1;
-  struct Par { double w2; };
-  __device__ static Par prep(const double (&th)[P]) { return Par{th[0] * th[0]}; }
-  __device__ static void f(double, const double (&y)[D], const Par& p, double (&dy)[D]) {
+  template <class T>
+  struct ParT { T w2; };
+  using Par = ParT<double>;
+  template <class T>
+  __device__ static ParT<T> prep(const T (&th)[P]) { return ParT<T>{th[0] * th[0]}; }
+  template <class T>
+  __device__ static void f(double, const T (&y)[D], const ParT<T>& p, T (&dy)[D]) {
     dy[0] = y[1];
     dy[1] = -p.w2 * y[0];
   }
@@ -55,11 +76,15 @@ struct Harmonic {
 // Planar Kepler problem: r'' = -mu r / |r|^3.  Closed-form test system.
 struct Kepler {
   static constexpr int D = 4, P = 1;
-  struct Par { double mu; };
-  __device__ static Par prep(const double (&th)[P]) { return Par{th[0]}; }
-  __device__ static void f(double, const double (&y)[D], const Par& p, double (&dy)[D]) {
-    const double r2 = y[0] * y[0] + y[1] * y[1];
-    const double ir3 = fast_rcp(r2 * sqrt(r2));
+  template <class T>
+  struct ParT { T mu; };
+  using Par = ParT<double>;
+  template <class T>
+  __device__ static ParT<T> prep(const T (&th)[P]) { return ParT<T>{th[0]}; }
+  template <class T>
+  __device__ static void f(double, const T (&y)[D], const ParT<T>& p, T (&dy)[D]) {
+    const T r2 = y[0] * y[0] + y[1] * y[1];
+    const T ir3 = fast_rcp(r2 * sqrt(r2));
     dy[0] = y[2];
     dy[1] = y[3];
     dy[2] = -p.mu * ir3 * y[0];
@@ -87,14 +112,18 @@ struct Kepler {
 // is a = -(v0^2 / D) g.
 struct LogHalo {
   static constexpr int D = 6, P = 3;
-  struct Par { double v02, iq2, rc2; };
-  __device__ static Par prep(const double (&th)[P]) {
-    const double iq = 1.0 / th[1];
-    return Par{th[0] * th[0], iq * iq, th[2] * th[2]};
+  template <class T>
+  struct ParT { T v02, iq2, rc2; };
+  using Par = ParT<double>;
+  template <class T>
+  __device__ static ParT<T> prep(const T (&th)[P]) {
+    const T iq = 1.0 / th[1];
+    return ParT<T>{th[0] * th[0], iq * iq, th[2] * th[2]};
   }
-  __device__ static void f(double, const double (&y)[D], const Par& p, double (&dy)[D]) {
-    const double Dn = fma(y[2] * y[2], p.iq2, fma(y[1], y[1], fma(y[0], y[0], p.rc2)));
-    const double s = -p.v02 * fast_rcp(Dn);
+  template <class T>
+  __device__ static void f(double, const T (&y)[D], const ParT<T>& p, T (&dy)[D]) {
+    const T Dn = fma(y[2] * y[2], p.iq2, fma(y[1], y[1], fma(y[0], y[0], p.rc2)));
+    const T s = -p.v02 * fast_rcp(Dn);
     dy[0] = y[3];
     dy[1] = y[4];
     dy[2] = y[5];
@@ -144,14 +173,17 @@ struct LogHalo {
 // f = (dL/dt, dS1/dt, dS2/dt) / (dv/dt).
 struct SpinPrec {
   static constexpr int D = 9, P = 3;
-  struct Par {
-    double q, iq, eta, ieta, S1, S2, cq1, cq2, c1, c2, sig, b2, b4c;
+  template <class T>
+  struct ParT {
+    T q, iq, eta, ieta, S1, S2, cq1, cq2, c1, c2, sig, b2, b4c;
   };
-  __device__ static Par prep(const double (&th)[P]) {
-    Par p;
-    const double q = th[0], chi1 = th[1], chi2 = th[2];
-    const double m1 = 1.0 / (1.0 + q);
-    const double m2 = q * m1;
+  using Par = ParT<double>;
+  template <class T>
+  __device__ static ParT<T> prep(const T (&th)[P]) {
+    ParT<T> p;
+    const T q = th[0], chi1 = th[1], chi2 = th[2];
+    const T m1 = 1.0 / (1.0 + q);
+    const T m2 = q * m1;
     p.q = q;
     p.iq = 1.0 / q;
     p.eta = m1 * m2;
@@ -168,12 +200,17 @@ struct SpinPrec {
     return p;
   }
 
-  // Shared forward pieces, also needed by the VJP.
-  struct Fwd {
-    double v2, v3, v4, v6h, L, Ls1, Ls2, s12, cL1, cL2;
-    double Om1[3], Om2[3], ds1[3], ds2[3], u[3], poly, k9, r;
+  // Shared forward pieces, also needed by the VJP (powers of v are plain
+  // doubles, everything else follows the scalar type).
+  template <class T>
+  struct FwdT {
+    double v2, v3, v4, v6h, k9;
+    T L, Ls1, Ls2, s12, cL1, cL2;
+    T Om1[3], Om2[3], ds1[3], ds2[3], u[3], poly, r;
   };
-  __device__ static void forward(double v, const double (&y)[D], const Par& p, Fwd& w) {
+  using Fwd = FwdT<double>;
+  template <class T>
+  __device__ static void forward(double v, const T (&y)[D], const ParT<T>& p, FwdT<T>& w) {
     w.v2 = v * v;
     w.v3 = w.v2 * v;
     w.v4 = w.v2 * w.v2;
@@ -198,16 +235,17 @@ struct SpinPrec {
     w.ds2[2] = w.Om2[0] * y[7] - w.Om2[1] * y[6];
 #pragma unroll
     for (int i = 0; i < 3; ++i) w.u[i] = p.S1 * w.ds1[i] + p.S2 * w.ds2[i];
-    const double beta = p.c1 * w.Ls1 + p.c2 * w.Ls2;
-    const double sigma = p.sig * (721.0 * w.Ls1 * w.Ls2 - 247.0 * w.s12);
+    const T beta = p.c1 * w.Ls1 + p.c2 * w.Ls2;
+    const T sigma = p.sig * (721.0 * w.Ls1 * w.Ls2 - 247.0 * w.s12);
     w.poly = 1.0 + p.b2 * w.v2 + (4.0 * M_PI - beta) * w.v3 + (p.b4c + sigma) * w.v4;
     w.k9 = 6.4 * v6 * w.v3;  // (32/5) v^9
     w.r = fast_rcp(w.k9 * p.eta * w.poly);
   }
-  __device__ static void f(double v, const double (&y)[D], const Par& p, double (&dy)[D]) {
-    Fwd w;
+  template <class T>
+  __device__ static void f(double v, const T (&y)[D], const ParT<T>& p, T (&dy)[D]) {
+    FwdT<T> w;
     forward(v, y, p, w);
-    const double cl = -v * p.ieta * w.r;
+    const T cl = -v * p.ieta * w.r;
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
       dy[i] = cl * w.u[i];
@@ -360,17 +398,21 @@ struct SpinPrec {
 //   phi' = u,  u' = -(3 + dlnE/dN) u + 3 lambda v / E^2,  I' = e^{-N} / E.
 struct Quint {
   static constexpr int D = 3, P = 4;
-  struct Par { double a0, lam, om, orad; };
-  __device__ static Par prep(const double (&th)[P]) { return Par{th[0], th[1], th[2], th[3]}; }
-  __device__ static void f(double N, const double (&y)[D], const Par& p, double (&dy)[D]) {
+  template <class T>
+  struct ParT { T a0, lam, om, orad; };
+  using Par = ParT<double>;
+  template <class T>
+  __device__ static ParT<T> prep(const T (&th)[P]) { return ParT<T>{th[0], th[1], th[2], th[3]}; }
+  template <class T>
+  __device__ static void f(double N, const T (&y)[D], const ParT<T>& p, T (&dy)[D]) {
     const double eN = exp(-N);
     const double e3 = eN * eN * eN;
     const double e4 = e3 * eN;
-    const double u = y[1];
-    const double pot = p.a0 * exp(-p.lam * y[0]);
-    const double den = 1.0 - u * u * (1.0 / 6.0);
-    const double iE2 = den * fast_rcp(p.om * e3 + p.orad * e4 + pot);
-    const double dlnE = -0.5 * (3.0 * p.om * e3 + 4.0 * p.orad * e4) * iE2 - 0.5 * u * u;
+    const T u = y[1];
+    const T pot = p.a0 * exp(-p.lam * y[0]);
+    const T den = 1.0 - u * u * (1.0 / 6.0);
+    const T iE2 = den * fast_rcp(p.om * e3 + p.orad * e4 + pot);
+    const T dlnE = -0.5 * (3.0 * p.om * e3 + 4.0 * p.orad * e4) * iE2 - 0.5 * u * u;
     dy[0] = u;
     dy[1] = -(3.0 + dlnE) * u + 3.0 * p.lam * pot * iE2;
     dy[2] = eN * sqrt(iE2);

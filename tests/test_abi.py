@@ -101,3 +101,16 @@ def test_wide_needs_queue_schedule_without_outputs_or_tape():
     for kw in (dict(wide=8, schedule=1), dict(wide=8, ckpt_every=4, ckpt_capacity=10),
                dict(wide=8, K=3, t_out=0x1000, y_out=0x1000)):
         assert api.lib().gs_solve(C.byref(_args(**kw))) == 2
+
+
+def test_sens_argument_checks():
+    a = _args()
+    cols = (C.c_int32 * 2)(0, 8)
+    ok = api.gs_sens_args(2, C.cast(cols, C.c_void_p), 0x1000, 0)
+    assert api.lib().gs_solve_sens(C.byref(_args()), None) == 1
+    assert api.lib().gs_solve_sens(C.byref(a), C.byref(api.gs_sens_args(0, C.cast(cols, C.c_void_p), 0x1000, 0))) == 1
+    bad = (C.c_int32 * 2)(0, 9)  # d + p = 9 columns exist
+    assert api.lib().gs_solve_sens(C.byref(a), C.byref(api.gs_sens_args(2, C.cast(bad, C.c_void_p), 0x1000, 0))) == 1
+    # no tape and no wide groups with sensitivities
+    assert api.lib().gs_solve_sens(C.byref(_args(ckpt_every=4, ckpt_capacity=10)), C.byref(ok)) == 2
+    assert api.lib().gs_solve_sens(C.byref(_args(wide=8)), C.byref(ok)) == 2

@@ -1,0 +1,71 @@
+"""Forward sensitivities on the GPU (gs_solve_sens): eq:sens carried through
+the stages (eq:stage-sens) in the same launch as the solution.
+
+The solution is the plain solve's, bit for bit (step control reads values
+only); the tangents are the oracle's forward sensitivities of the same
+discrete solution, at the output nodes and at t1, up to rounding.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from gpu_util import gpu_solve, oracle_solve, to_np  # noqa: E402
+from paper_2609_28458_amd import api, inputs  # noqa: E402
+from test_gpu_forward import CASES  # noqa: E402
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a GPU")
+    api.lib()
+
+
+def _prob(w):
+    return api.make_problem(w["rhs"], w["tableau"], w["y0"], w["theta"], w["t0"], w["t1"],
+                            w["rtol"], w["atol"], w.get("t_out"))
+
+
+def _close(got, ref, tol=1e-9):
+    # relative to the largest sensitivity of the trajectory (floor 1)
+    scale = np.maximum(np.abs(ref).reshape(-1, ref.shape[-1]).max(axis=0), 1.0)
+    err = np.abs(got - ref) / scale
+    assert err.max() < tol, err.max()
+
+
+@pytest.mark.parametrize("tab", ["dopri5", "tsit5", "verner7"])
+@pytest.mark.parametrize("name,make", CASES, ids=[c[0] for c in CASES])
+def test_sensitivities_match_oracle(orc, name, make, tab):
+    w = {**make(150), "tableau": tab}
+    prob = _prob(w)
+    d, p = prob.d, api.NPARAM[prob.rhs]
+    cols = [0, d + p - 1, d - 1]  # an initial condition, a parameter, another state; 2 launches
+    sol, S_final, S_out = api.solve_sens(prob, cols)
+    torch.cuda.synchronize()
+    g = to_np(sol)
+    ref = to_np(gpu_solve(w))
+    for k in ref:
+        np.testing.assert_array_equal(g[k], ref[k], err_msg=k)
+    assert np.all(g["status"] == 0)
+    o = oracle_solve(orc, w, sens_cols=cols)
+    np.testing.assert_array_equal(g["n_accepted"], o["n_accepted"])
+    _close(S_final.cpu().numpy(), o["S_final"])
+    if S_out is not None:
+        _close(S_out.cpu().numpy(), o["S_out"])
+
+
+def test_sensitivities_of_the_gradient_workload(orc):
+    """100,000 orbits to t = 100 with the two halo parameters (v0, q) as
+    columns, the paper's stream-gradient setting: sampled against the
+    oracle."""
+    w = inputs.orbits_gradient()
+    prob = _prob(w)
+    sol, S_final, _ = api.solve_sens(prob, [6, 7])
+    torch.cuda.synchronize()
+    assert bool((sol.status == 0).all())
+    idx = np.sort(np.random.default_rng(21).choice(prob.n, 200, replace=False))
+    o = oracle_solve(orc, w, idx, sens_cols=[6, 7])
+    np.testing.assert_array_equal(sol.n_accepted.cpu().numpy()[idx], o["n_accepted"])
+    _close(S_final.cpu().numpy()[:, :, idx], o["S_final"])
