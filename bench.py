@@ -323,6 +323,14 @@ def main():
                        "ms_forward_tape_plus_vjp": round(best[1], 4), "ckpt_every": best[0],
                        "ms_by_ckpt_every": per_k}
         out["grad_forward_ratio"] = best[1] / ms_fwd
+        # The paper's own derivative: forward sensitivities in the same launch,
+        # two columns (v0, q) as in its stream gradients, and all nine inputs.
+        sens = {}
+        for cols in ([6, 7], list(range(9))):
+            ms_s = timed(lambda: api.solve_sens(pg, cols), max(3, args.steps // 4), 1, torch)
+            sens[str(len(cols))] = {"ms": round(ms_s, 4), "ratio": round(ms_s / ms_fwd, 3)}
+        out["grad"]["forward_sensitivities_by_columns"] = sens
+        log(f"[bench] forward sensitivities: {sens}")
 
     if not args.no_cpu:
         cb = cpu_baseline(w)
