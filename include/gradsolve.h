@@ -233,6 +233,59 @@ typedef struct gs_sens_args {
 
 gs_status gs_solve_sens(const gs_solve_args* args, const gs_sens_args* sens);
 
+/* Profile likelihood of the dark-energy slope (Section "A profile
+ * likelihood" and its appendix "Data model and minimiser"): n independent
+ * damped Gauss-Newton fits (eq:de-gn) of psi = (Omega_m, h), h = H0 over a
+ * reference, at fixed slope lambda[i], for the quintessence system
+ * (gs_rhs_quint) with the amplitude a0 solved for flatness E(0) = 1 by
+ * Newton steps on the sensitivity S_a0 (the shooting method, eq:de-flat)
+ * and the derivative along flat models from the implicit-function theorem
+ * (eq:de-ift); both sensitivities come from the same ensemble solve
+ * (gs_solve_sens).  Model distances are D_M = (I(0) - I(N_k)) / h and
+ * D_H = 1 / (h E(N_k)) in reference Hubble distances; residuals
+ * r = (model - data) / sigma, D_M at every node then D_H.
+ *
+ * Each iteration: `newton` shooting steps, one solve with both
+ * sensitivities at the K nodes, then the update psi <- psi -
+ * (J^T J + mu diag J^T J)^{-1} J^T r, scaled back into the box
+ * |dOmega_m| <= trust_om, |dh| <= trust_h, and a0 moved by
+ * (da0/dOmega_m) dOmega_m.  After the iterations the amplitude is shot again
+ * and chi2 (and dist, if given) are evaluated at the returned parameters.
+ * All arrays are device memory, trajectory index fastest; the call
+ * allocates nothing (workspace: gs_de_profile_workspace_bytes, 256-byte
+ * aligned) and only enqueues work on `stream`. */
+typedef struct gs_de_profile_args {
+  int64_t n;                /* minimisations                                */
+  const double* lambda;     /* [n] fixed slope                              */
+  double* omega_m;          /* [n] in: start; out: fitted                   */
+  double* h;                /* [n] in: start; out: fitted                   */
+  double* a0;               /* [n] in: start amplitude; out: flat amplitude
+                               at the fitted parameters                     */
+  double omega_r;           /* radiation density (shared)                   */
+  int32_t K;                /* nodes, >= 1                                  */
+  const double* N_nodes;    /* [K] e-folds N = -ln(1+z), increasing, <= 0   */
+  const double* data;       /* [2][K][n] D_M then D_H                       */
+  const double* sigma;      /* [2][K]                                       */
+  int32_t iters;            /* Gauss-Newton iterations                      */
+  int32_t newton;           /* shooting steps per iteration                 */
+  double mu;                /* damping of eq:de-gn                          */
+  double trust_om, trust_h; /* trust box half-widths                        */
+  int32_t tableau;          /* gs_tableau_id of the solves                  */
+  double N_start;           /* initial e-fold, < 0 (field at rest there)    */
+  double rtol, atol;
+  double* chi2;             /* [n] out: at the returned parameters          */
+  double* chi2_prev;        /* [n] out: before the last update              */
+  double* decrement;        /* [n] out: g^T step of the last update         */
+  double* dist;             /* [2][K][n] out: model distances, or NULL      */
+  int32_t* status;          /* [n] out: worst gs_traj_status of all solves  */
+  void* workspace;
+  size_t workspace_bytes;
+  void* stream;             /* hipStream_t                                  */
+} gs_de_profile_args;
+
+size_t gs_de_profile_workspace_bytes(const gs_de_profile_args* args);
+gs_status gs_de_profile(const gs_de_profile_args* args);
+
 /* Solution at arbitrary times t_query [Q][n] (each in [t0, t1]) from the tape
  * of the last gs_solve with `fwd` (eq:dense; replay from the nearest
  * checkpoint, or from t0 when no tape was kept).  y_query is [d][Q][n]. */

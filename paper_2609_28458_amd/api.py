@@ -16,6 +16,7 @@ import ctypes as C
 import os
 from dataclasses import dataclass
 
+import numpy as np
 import torch
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -72,8 +73,21 @@ class gs_sens_args(C.Structure):
     ]
 
 
+class gs_de_profile_args(C.Structure):
+    _fields_ = [
+        ("n", C.c_int64), ("lambda_", C.c_void_p), ("omega_m", C.c_void_p), ("h", C.c_void_p),
+        ("a0", C.c_void_p), ("omega_r", C.c_double), ("K", C.c_int32), ("N_nodes", C.c_void_p),
+        ("data", C.c_void_p), ("sigma", C.c_void_p), ("iters", C.c_int32), ("newton", C.c_int32),
+        ("mu", C.c_double), ("trust_om", C.c_double), ("trust_h", C.c_double),
+        ("tableau", C.c_int32), ("N_start", C.c_double), ("rtol", C.c_double),
+        ("atol", C.c_double), ("chi2", C.c_void_p), ("chi2_prev", C.c_void_p),
+        ("decrement", C.c_void_p), ("dist", C.c_void_p), ("status", C.c_void_p),
+        ("workspace", C.c_void_p), ("workspace_bytes", C.c_size_t), ("stream", C.c_void_p),
+    ]
+
+
 EXPORTS = ["gs_default_args", "gs_workspace_bytes", "gs_solve", "gs_solve_vjp", "gs_solve_sens",
-           "gs_dense_eval",
+           "gs_de_profile", "gs_de_profile_workspace_bytes", "gs_dense_eval",
            "gs_rhs_eval", "gs_graph_create", "gs_graph_launch", "gs_graph_destroy",
            "gs_status_string", "gs_version"]
 
@@ -98,6 +112,10 @@ def lib():
         L.gs_solve_vjp.restype = C.c_int
         L.gs_solve_sens.argtypes = [C.POINTER(gs_solve_args), C.POINTER(gs_sens_args)]
         L.gs_solve_sens.restype = C.c_int
+        L.gs_de_profile.argtypes = [C.POINTER(gs_de_profile_args)]
+        L.gs_de_profile.restype = C.c_int
+        L.gs_de_profile_workspace_bytes.argtypes = [C.POINTER(gs_de_profile_args)]
+        L.gs_de_profile_workspace_bytes.restype = C.c_size_t
         L.gs_dense_eval.argtypes = [C.POINTER(gs_solve_args), C.c_int32, C.c_void_p, C.c_void_p,
                                     C.c_void_p]
         L.gs_dense_eval.restype = C.c_int
@@ -356,6 +374,56 @@ def solve_sens(prob: Problem, cols, launch: Launch | None = None, stream=None):
     sol.args.stream = _stream_handle(stream)
     gs_solve_sens(sol.args, s)
     return sol, S_final, S_out
+
+
+def gs_de_profile(args: gs_de_profile_args) -> None:
+    _check(lib().gs_de_profile(C.byref(args)))
+
+
+def de_profile(lam, omega_m, h, a0, omega_r, N_nodes, data, sigma, *, iters=20, newton=3,
+               mu=1e-3, trust=(0.05, 0.05), tableau="dopri5", N_start=None, rtol=1.78e-4,
+               atol=1.78e-7, device="cuda", stream=None):
+    """Dark-energy profile fits (gs_de_profile): n minimisations at fixed
+    lam [n], psi = (omega_m, h) from the given starts, a0 [n] the starting
+    amplitudes; data [2][K][n], sigma [2][K].  Returns a dict of device
+    tensors: omega_m, h, a0, chi2, chi2_prev, decrement, dist [2][K][n],
+    status."""
+    f64 = dict(dtype=torch.float64, device=device)
+    lam_t = torch.as_tensor(lam, **f64).contiguous()
+    n = lam_t.numel()
+    out = {"omega_m": torch.as_tensor(omega_m, **f64).clone().contiguous(),
+           "h": torch.as_tensor(h, **f64).clone().contiguous(),
+           "a0": torch.as_tensor(a0, **f64).clone().contiguous()}
+    Nn = torch.as_tensor(N_nodes, **f64).contiguous()
+    K = Nn.numel()
+    data_t = torch.as_tensor(data, **f64).contiguous()
+    sig_t = torch.as_tensor(sigma, **f64).contiguous()
+    if tuple(data_t.shape) != (2, K, n) or tuple(sig_t.shape) != (2, K):
+        raise ValueError("data must be [2][K][n] and sigma [2][K]")
+    for k in ("chi2", "chi2_prev", "decrement"):
+        out[k] = torch.empty(n, **f64)
+    out["dist"] = torch.empty((2, K, n), **f64)
+    out["status"] = torch.empty(n, dtype=torch.int32, device=device)
+    a = gs_de_profile_args()
+    a.n, a.lambda_, a.omega_m, a.h, a.a0 = n, _ptr(lam_t), _ptr(out["omega_m"]), _ptr(out["h"]), \
+        _ptr(out["a0"])
+    a.omega_r, a.K, a.N_nodes, a.data, a.sigma = float(omega_r), K, _ptr(Nn), _ptr(data_t), \
+        _ptr(sig_t)
+    a.iters, a.newton, a.mu = int(iters), int(newton), float(mu)
+    a.trust_om, a.trust_h = float(trust[0]), float(trust[1])
+    a.tableau = TABLEAU[tableau] if isinstance(tableau, str) else int(tableau)
+    a.N_start = float(-np.log(51.0) if N_start is None else N_start)
+    a.rtol, a.atol = float(rtol), float(atol)
+    a.chi2, a.chi2_prev, a.decrement = _ptr(out["chi2"]), _ptr(out["chi2_prev"]), \
+        _ptr(out["decrement"])
+    a.dist, a.status = _ptr(out["dist"]), _ptr(out["status"])
+    nbytes = int(lib().gs_de_profile_workspace_bytes(C.byref(a)))
+    ws = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=device)
+    a.workspace, a.workspace_bytes = ws.data_ptr(), ws.numel()
+    a.stream = _stream_handle(stream)
+    gs_de_profile(a)
+    out["_keep"] = (lam_t, Nn, data_t, sig_t, ws)
+    return out
 
 
 def solve_vjp(sol: Solution, ybar_final=None, ybar_out=None, block=0, grid=0, stream=None):

@@ -10,6 +10,7 @@
 #include <mutex>
 
 #include "gradsolve.h"
+#include "gs_de.hpp"
 #include "gs_kernels.hpp"
 #include "gs_ops.hpp"
 
@@ -334,15 +335,9 @@ gs_status gs_solve_vjp(const gs_solve_args* fwd, const gs_vjp_args* v) {
   return hipGetLastError() == hipSuccess ? GS_OK : GS_ERR_HIP;
 }
 
-gs_status gs_solve_sens(const gs_solve_args* a, const gs_sens_args* sa) {
-  gs_status st = check_args(a);
-  if (st != GS_OK) return st;
-  if (!sa || sa->M < 1 || sa->M > kSensMaxCols || !sa->cols || !sa->S_final) return GS_ERR_INVALID;
-  if (a->K > 0 && !sa->S_out) return GS_ERR_INVALID;
-  if (a->ckpt_every > 0 || a->wide > 0 || a->schedule != GS_SCHED_QUEUE) return GS_ERR_UNSUPPORTED;
-  for (int m = 0; m < sa->M; ++m)
-    if (sa->cols[m] < 0 || sa->cols[m] >= a->d + a->p) return GS_ERR_INVALID;
-  if (a->n == 0) return GS_OK;
+namespace {
+// The launches of a sensitivity solve whose arguments have been checked.
+void sens_launches(const gs_solve_args* a, const gs_sens_args* sa) {
   hipStream_t s = static_cast<hipStream_t>(a->stream);
   const Params P = make_params(a);
   const int block = a->block > 0 ? a->block : 256;
@@ -369,6 +364,166 @@ gs_status gs_solve_sens(const gs_solve_args* a, const gs_sens_args* sa) {
     hipLaunchKernelGGL(reset_queues_kernel, dim3(1), dim3(64), 0, s, P.counters, 0ll);
     ops(a->rhs, a->tableau).sens(P, S, mm, grid, block, s);
   }
+}
+
+// Workspace of gs_de_profile: solver counters, device scalars (t0, t1, rtol,
+// atol), theta [4][n], y0 [3][n], y_out [3][K][n], y_final [3][n],
+// S_out [3][2][K][n], S_final [3][2][n], and three int32 [n] arrays.
+struct DeLayout {
+  size_t counters, scal, theta, y0, y_out, y_final, S_out, S_final, nacc, nrej, st, total;
+};
+DeLayout de_layout(const gs_de_profile_args* A) {
+  DeLayout L;
+  const size_t n = (size_t)A->n, K = (size_t)A->K;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = off;
+    off = align256(off + bytes);
+    return at;
+  };
+  L.counters = take(kCounterBytes);
+  L.scal = take(4 * 8);
+  L.theta = take(4 * n * 8);
+  L.y0 = take(3 * n * 8);
+  L.y_out = take(3 * K * n * 8);
+  L.y_final = take(3 * n * 8);
+  L.S_out = take(3 * 2 * K * n * 8);
+  L.S_final = take(3 * 2 * n * 8);
+  L.nacc = take(n * 4);
+  L.nrej = take(n * 4);
+  L.st = take(n * 4);
+  L.total = off;
+  return L;
+}
+
+__global__ void de_setup_kernel(int64_t n, double* scal, double t0, double rtol, double atol,
+                                double* y0) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i == 0) {
+    scal[0] = t0;
+    scal[1] = 0.0;
+    scal[2] = rtol;
+    scal[3] = atol;
+  }
+  if (i < 3 * n) y0[i] = 0.0;
+}
+}  // namespace
+
+gs_status gs_solve_sens(const gs_solve_args* a, const gs_sens_args* sa) {
+  gs_status st = check_args(a);
+  if (st != GS_OK) return st;
+  if (!sa || sa->M < 1 || sa->M > kSensMaxCols || !sa->cols || !sa->S_final) return GS_ERR_INVALID;
+  if (a->K > 0 && !sa->S_out) return GS_ERR_INVALID;
+  if (a->ckpt_every > 0 || a->wide > 0 || a->schedule != GS_SCHED_QUEUE) return GS_ERR_UNSUPPORTED;
+  for (int m = 0; m < sa->M; ++m)
+    if (sa->cols[m] < 0 || sa->cols[m] >= a->d + a->p) return GS_ERR_INVALID;
+  if (a->n == 0) return GS_OK;
+  sens_launches(a, sa);
+  return hipGetLastError() == hipSuccess ? GS_OK : GS_ERR_HIP;
+}
+
+size_t gs_de_profile_workspace_bytes(const gs_de_profile_args* A) {
+  if (!A || A->n < 0 || A->K < 1) return 0;
+  return de_layout(A).total;
+}
+
+gs_status gs_de_profile(const gs_de_profile_args* A) {
+  if (!A || A->n < 0 || A->K < 1 || A->iters < 0 || A->newton < 0) return GS_ERR_INVALID;
+  if (A->tableau < 0 || A->tableau >= kNumTab || !(A->rtol > 0.0) || !(A->atol >= 0.0) ||
+      !(A->N_start < 0.0) || !(A->mu >= 0.0) || !(A->trust_om > 0.0) || !(A->trust_h > 0.0))
+    return GS_ERR_INVALID;
+  if (A->n == 0) return GS_OK;
+  if (!A->lambda || !A->omega_m || !A->h || !A->a0 || !A->N_nodes || !A->data || !A->sigma ||
+      !A->chi2 || !A->chi2_prev || !A->decrement || !A->status)
+    return GS_ERR_INVALID;
+  if (!A->workspace || ((uintptr_t)A->workspace & 255) != 0 ||
+      A->workspace_bytes < de_layout(A).total)
+    return GS_ERR_WORKSPACE;
+  const DeLayout L = de_layout(A);
+  char* ws = static_cast<char*>(A->workspace);
+  auto D = [&](size_t off) { return reinterpret_cast<double*>(ws + off); };
+  auto I = [&](size_t off) { return reinterpret_cast<int32_t*>(ws + off); };
+  const int64_t n = A->n;
+  const int blk = 256;
+  const int grd = (int)((n + blk - 1) / blk);
+  const int grd3 = (int)((3 * n + blk - 1) / blk);
+  hipStream_t s = static_cast<hipStream_t>(A->stream);
+  hipLaunchKernelGGL(de_setup_kernel, dim3(grd3), dim3(blk), 0, s, n, D(L.scal), A->N_start,
+                     A->rtol, A->atol, D(L.y0));
+  hipLaunchKernelGGL(gs::de::init_kernel, dim3(grd), dim3(blk), 0, s, n, A->a0, A->lambda,
+                     A->omega_m, A->omega_r, D(L.theta), A->status);
+  // The ensemble solve of the quintessence system for the current theta.
+  gs_solve_args a;
+  gs_default_args(&a);
+  a.rhs = GS_RHS_QUINT;
+  a.tableau = A->tableau;
+  a.n = n;
+  a.d = 3;
+  a.p = 4;
+  a.y0 = D(L.y0);
+  a.theta = D(L.theta);
+  a.theta_stride = n;
+  a.t0 = D(L.scal);
+  a.t1 = D(L.scal) + 1;
+  a.rtol = D(L.scal) + 2;
+  a.atol = D(L.scal) + 3;
+  a.t_out = A->N_nodes;
+  a.y_out = D(L.y_out);
+  a.y_final = D(L.y_final);
+  a.n_accepted = I(L.nacc);
+  a.n_rejected = I(L.nrej);
+  a.status = I(L.st);
+  a.workspace = ws + L.counters;
+  a.workspace_bytes = kCounterBytes;
+  a.stream = A->stream;
+  const int32_t col_a0[1] = {3};          // d/da0
+  const int32_t col_both[2] = {3, 5};     // d/da0, d/dOm
+  gs_sens_args one{1, col_a0, D(L.S_final), nullptr};
+  gs_sens_args both{2, col_both, D(L.S_final), D(L.S_out)};
+  auto shoot = [&]() {
+    a.K = 0;
+    for (int j = 0; j < A->newton; ++j) {
+      sens_launches(&a, &one);
+      hipLaunchKernelGGL(gs::de::shoot_kernel, dim3(grd), dim3(blk), 0, s, n, D(L.theta),
+                         D(L.y_final), D(L.S_final), I(L.st), A->status);
+    }
+    a.K = A->K;
+  };
+  gs::de::GnArgs g;
+  g.n = n;
+  g.K = A->K;
+  g.N_nodes = A->N_nodes;
+  g.y_out = D(L.y_out);
+  g.y_final = D(L.y_final);
+  g.S_out = D(L.S_out);
+  g.S_final = D(L.S_final);
+  g.data = A->data;
+  g.sigma = A->sigma;
+  g.status = I(L.st);
+  g.mu = A->mu;
+  g.trust_om = A->trust_om;
+  g.trust_h = A->trust_h;
+  g.theta = D(L.theta);
+  g.h = A->h;
+  g.chi2 = A->chi2;
+  g.chi2_prev = A->chi2_prev;
+  g.decrement = A->decrement;
+  g.status_out = A->status;
+  for (int it = 0; it < A->iters; ++it) {
+    shoot();
+    sens_launches(&a, &both);
+    g.update = 1;
+    g.dist = nullptr;
+    hipLaunchKernelGGL(gs::de::gn_kernel, dim3(grd), dim3(blk), 0, s, g);
+  }
+  // chi2 and distances at the returned parameters, the amplitude flat there
+  shoot();
+  sens_launches(&a, &both);
+  g.update = 0;
+  g.dist = A->dist;
+  hipLaunchKernelGGL(gs::de::gn_kernel, dim3(grd), dim3(blk), 0, s, g);
+  hipLaunchKernelGGL(gs::de::finish_kernel, dim3(grd), dim3(blk), 0, s, n, D(L.theta), A->a0,
+                     A->omega_m);
   return hipGetLastError() == hipSuccess ? GS_OK : GS_ERR_HIP;
 }
 
