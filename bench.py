@@ -332,6 +332,54 @@ def main():
         out["grad"]["forward_sensitivities_by_columns"] = sens
         log(f"[bench] forward sensitivities: {sens}")
 
+    # ---- dark-energy profile likelihood: 100 mocks x 100 slopes --------------------------
+    if not args.no_grad:
+        wd = inputs.de_profile_mocks()
+        f = wd["fid"]
+        kw = dict(newton=wd["newton"], mu=wd["mu"], trust=wd["trust"], rtol=wd["rtol"],
+                  atol=wd["atol"], N_start=wd["t0"])
+        K = len(wd["N_nodes"])
+        fid = api.de_profile([f["lam"]], [f["om"]], [f["h"]], [1.0 - f["om"] - wd["omega_r"]],
+                             wd["omega_r"], wd["N_nodes"], np.zeros((2, K, 1)), np.ones((2, K)),
+                             iters=0, **kw)
+        dfid = fid["dist"][:, :, 0]
+        nm, nl = wd["eps"].shape[0], len(wd["lam_grid"])
+        nfit = nm * nl
+        eps = torch.as_tensor(wd["eps"], device="cuda")[torch.arange(nfit, device="cuda") // nl]
+        data = (dfid[:, :, None] * (1.0 + wd["rel_noise"] * eps.permute(1, 2, 0))).contiguous()
+        sigma = (wd["rel_noise"] * dfid).contiguous()
+        dev = dict(dtype=torch.float64, device="cuda")
+        lam = torch.as_tensor(np.tile(wd["lam_grid"], nm), **dev)
+        om0 = torch.full((nfit,), wd["start"]["om"], **dev)
+        h0 = torch.full((nfit,), wd["start"]["h"], **dev)
+        a00 = 1.0 - om0 - wd["omega_r"]
+        Nn = torch.as_tensor(wd["N_nodes"], **dev)
+
+        prof = {"workload": f"{nm} mocks x {nl} slopes = {nfit} Gauss-Newton fits, "
+                            f"{wd['iters']} iterations, 7 nodes"}
+        # "a0 supplied": the flat amplitude at the start is handed in and moved to first order
+        # with da0/dOm (no shooting in the timed fits)
+        a0_flat = api.de_profile(lam, om0, h0, a00, wd["omega_r"], Nn, data, sigma, iters=0,
+                                 **kw)["a0"]
+        for name, newton, a0s in (("a0_solved", wd["newton"], a00), ("a0_supplied", 0, a0_flat)):
+            def profile():
+                return api.de_profile(lam, om0, h0, a0s, wd["omega_r"], Nn, data, sigma,
+                                      iters=wd["iters"], **dict(kw, newton=newton))
+
+            ms_p = timed(profile, max(3, args.steps // 4), 1, torch)
+            res = profile()
+            torch.cuda.synchronize()
+            conv = ((res["chi2_prev"] - res["chi2"]).abs() < 1e-4) & \
+                (res["decrement"].abs() < 1e-6)
+            us_it = ms_p * 1e3 / (nfit * wd["iters"])
+            prof[name] = {"newton_steps": newton, "ms": round(ms_p, 4),
+                          "us_per_iteration_per_fit": round(us_it, 4),
+                          "converged_fraction": round(float(conv.float().mean()), 4),
+                          "all_ok": bool((res["status"] == 0).all())}
+            log(f"[bench] dark-energy profile ({name}): {ms_p:.3f} ms, "
+                f"{us_it:.4f} us per iteration per fit")
+        out["de_profile"] = prof
+
     if not args.no_cpu:
         cb = cpu_baseline(w)
         out["cpu_baseline"] = cb
