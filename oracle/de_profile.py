@@ -12,6 +12,10 @@ order of the paper's Section "A profile likelihood" and its appendix
   da0/dOm = -(dg/dOm)/(dg/da0), dy/dOm = S_Om + (da0/dOm) S_a0 (eq:de-ift);
 * distances D_M = (I(0) - I(N_z))/h and D_H = 1/(h E(N_z)) in units of the
   reference Hubble distance, h = H0 / H0_ref entering only as a scale;
+* optionally (appendix "Data model and minimiser") the model distances at
+  the data redshifts are read off a cubic spline in ln(1+z) through the node
+  values; the spline is scipy's not-a-knot CubicSpline, a linear map, so the
+  derivatives go through the same spline;
 * whitened residuals r = (D_model - D_data)/sigma and the damped Gauss-Newton
   update psi <- psi - (J^T J + mu diag J^T J)^{-1} J^T r over psi = (Om, h)
   (eq:de-gn), the step scaled back into a box trust region; before each
@@ -22,6 +26,7 @@ State y = (phi, u, I); theta = (a0, lambda, Om, Or).
 from __future__ import annotations
 
 import numpy as np
+from scipy.interpolate import CubicSpline
 
 import oracle
 
@@ -99,13 +104,27 @@ def model(a0, lam, om, h, orad, N_nodes, settings):
     return D, dD_om, -D / h, da0, Nm0 / Dn0, int(o["status"].max())
 
 
+def at_data(Dnode, N_nodes, N_data):
+    """Node values [2][K][n] -> values at the data e-folds [2][Kd][n] by a
+    not-a-knot cubic spline in x = ln(1+z) = -N (None: the data sit at the
+    nodes)."""
+    if N_data is None:
+        return Dnode
+    x = -np.asarray(N_nodes, dtype=np.float64)
+    order = np.argsort(x)
+    spl = CubicSpline(x[order], Dnode[:, order, :], axis=1)
+    return spl(-np.asarray(N_data, dtype=np.float64))
+
+
 def profile(lam, om, h, a0, orad, N_nodes, data, sigma, settings, iters=20, newton=3,
-            mu=1e-3, trust=(0.05, 0.05)):
+            mu=1e-3, trust=(0.05, 0.05), N_data=None):
     """Damped Gauss-Newton fits of psi = (Om, h) at fixed lam (one per column
-    of the inputs), a0 solved by shooting.  data [2][K][n], sigma [2][K].
-    Returns a dict: om, h, a0 (flat at the returned parameters), chi2 there,
-    chi2_prev (before the last update), decrement (last g^T step), dist (the
-    model distances at the returned parameters)."""
+    of the inputs), a0 solved by shooting.  data [2][Kd][n], sigma [2][Kd]
+    at the nodes (Kd = K) or, with N_data [Kd], at those e-folds through the
+    spline of `at_data`.  Returns a dict: om, h, a0 (flat at the returned
+    parameters), chi2 there, chi2_prev (before the last update), decrement
+    (last g^T step), dist (the model distances at the data points at the
+    returned parameters)."""
     om = np.array(om, dtype=np.float64)
     h = np.array(h, dtype=np.float64)
     a0 = np.array(a0, dtype=np.float64)
@@ -114,7 +133,9 @@ def profile(lam, om, h, a0, orad, N_nodes, data, sigma, settings, iters=20, newt
     dec = np.full(om.shape, np.nan)
     for _ in range(iters):
         a0 = flat_amplitude(a0, lam, om, orad, settings, newton)
-        D, dDo, dDh, da0, _, _ = model(a0, lam, om, h, orad, N_nodes, settings)
+        D, dDo, _, da0, _, _ = model(a0, lam, om, h, orad, N_nodes, settings)
+        D, dDo = at_data(D, N_nodes, N_data), at_data(dDo, N_nodes, N_data)
+        dDh = -D / h
         r = ((D - data) / sig).reshape(-1, om.size)
         J = np.stack([(dDo / sig).reshape(-1, om.size), (dDh / sig).reshape(-1, om.size)])
         A11 = np.sum(J[0] * J[0], axis=0)
@@ -137,6 +158,7 @@ def profile(lam, om, h, a0, orad, N_nodes, data, sigma, settings, iters=20, newt
         a0 = a0 - da0 * s1          # move the amplitude to the new Om
     a0 = flat_amplitude(a0, lam, om, orad, settings, newton)
     D, _, _, _, _, st = model(a0, lam, om, h, orad, N_nodes, settings)
+    D = at_data(D, N_nodes, N_data)
     chi2 = np.sum((((D - data) / sig) ** 2).reshape(-1, om.size), axis=0)
     return dict(om=om, h=h, a0=a0, chi2=chi2, chi2_prev=chi2_prev, decrement=dec, dist=D,
                 status=st)

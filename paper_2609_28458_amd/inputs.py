@@ -139,11 +139,15 @@ def de_profile_mocks(n_mocks=100, n_lambda=100, seed=6, omega_r=9.0e-5):
     [0, 1.5], and every minimisation started at Omega_m 0.30, h 1 and the
     frozen-field amplitude.  Minimisation i uses mock i // n_lambda and slope
     lam_grid[i % n_lambda].  Only the draws live here: the data are
-    D_fid (1 + rel_noise * eps), D_fid from whichever solver runs the fit."""
+    D_fid (1 + rel_noise * eps), D_fid from whichever solver runs the fit.
+    N_spline holds the 64 dense nodes of `quintessence` through which the
+    profile's spline reads the model at the data redshifts."""
     rng = _rng(seed)
     q = quintessence(n=1, omega_r=omega_r)
+    qd = quintessence(n=1, dense=True, omega_r=omega_r)
     return dict(lam_grid=np.linspace(0.0, 1.5, n_lambda), eps=rng.normal(size=(n_mocks, 2, 7)),
                 rel_noise=0.01, fid=dict(lam=0.8, om=0.31, h=1.0), start=dict(om=0.30, h=1.0),
-                omega_r=omega_r, N_nodes=q["t_out"], z_nodes=q["z_nodes"], t0=q["t0"],
+                omega_r=omega_r, N_nodes=q["t_out"], z_nodes=q["z_nodes"],
+                N_spline=qd["t_out"], t0=q["t0"],
                 tableau="dopri5", rtol=q["rtol"], atol=q["atol"], iters=20, newton=3,
                 mu=1e-3, trust=(0.05, 0.05))

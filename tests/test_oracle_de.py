@@ -94,3 +94,63 @@ def test_gauss_newton_recovers_noise_free_fiducial(de):
                      iters=w["iters"], newton=w["newton"], mu=w["mu"], trust=w["trust"])
     assert abs(out["om"][0] - f["om"]) < 1e-7 and abs(out["h"][0] - f["h"]) < 1e-7
     assert out["chi2"][0] < 1e-10
+
+
+def test_spline_reproduces_cubics_in_ln1pz(de):
+    """A not-a-knot cubic spline is exact on cubic polynomials of its
+    variable; a spline in z or with the nodes taken out of order is not."""
+    N_nodes = inputs.quintessence(n=1, dense=True)["t_out"]
+    N_data = inputs.quintessence(n=1)["t_out"]
+    x_n, x_d = -N_nodes, -N_data
+
+    def cubic(x):
+        return np.stack([0.3 - 1.1 * x + 0.7 * x ** 2 - 0.45 * x ** 3,
+                         2.0 + 0.2 * x - 0.9 * x ** 3])[:, :, None] * np.array([1.0, -2.0])
+
+    got = de.at_data(cubic(x_n), N_nodes, N_data)
+    np.testing.assert_allclose(got, cubic(x_d), rtol=0, atol=1e-13)
+    assert de.at_data(cubic(x_n), N_nodes, None) is not None
+
+
+def test_spline_profile_with_data_at_nodes_equals_direct(de):
+    """With the data redshifts among the spline nodes the spline returns the
+    node values, so the fit equals the fit with the nodes at the data (the
+    solver's steps do not depend on the output times)."""
+    w = inputs.de_profile_mocks(n_mocks=1, n_lambda=1)
+    s = dict(tableau=w["tableau"], t0=w["t0"], rtol=w["rtol"], atol=w["atol"])
+    orad = w["omega_r"]
+    N_data = w["N_nodes"]
+    N_nodes = np.unique(np.concatenate([N_data, w["N_spline"]]))
+    lam = np.array([0.4, 1.3])
+    om = np.array([0.30, 0.32])
+    a0 = de.flat_amplitude(1.0 - om - orad, lam, om, orad, s, 4)
+    D = de.model(a0, lam, om, np.ones(2), orad, N_data, s)[0] * 1.01
+    sigma = 0.01 * D[:, :, 0]
+    kw = dict(iters=4, newton=2, mu=w["mu"], trust=w["trust"])
+    start = (np.full(2, 0.29), np.full(2, 0.98), 1.0 - np.full(2, 0.29) - orad)
+    a = de.profile(lam, *start[:2], start[2], orad, N_data, D, sigma, s, **kw)
+    b = de.profile(lam, *start[:2], start[2], orad, N_nodes, D, sigma, s, N_data=N_data, **kw)
+    for k in ("om", "h", "a0", "chi2", "decrement"):
+        np.testing.assert_allclose(b[k], a[k], rtol=1e-12, atol=1e-14)
+
+
+def test_spline_distances_of_lcdm(de):
+    """64-node spline of the distances at lambda = 0 against the quadratures
+    at the 7 data redshifts: the spline error of smooth distances."""
+    orad = 9.0e-5
+    om = np.array([0.28, 0.34])
+    lam = np.zeros(2)
+    N_nodes = inputs.quintessence(n=1, dense=True)["t_out"]
+    z_data = inputs.quintessence(n=1)["z_nodes"]
+    a0 = 1.0 - om - orad
+    D = de.at_data(de.model(a0, lam, om, np.ones(2), orad, N_nodes, TIGHT)[0], N_nodes,
+                   -np.log1p(z_data))
+
+    def E(zz, m):
+        return np.sqrt(m * (1 + zz) ** 3 + orad * (1 + zz) ** 4 + 1.0 - m - orad)
+
+    for i, m in enumerate(om):
+        for k, zz in enumerate(z_data):
+            dm = quad(lambda x: 1.0 / E(x, m), 0.0, zz, epsabs=1e-14, epsrel=1e-13)[0]
+            assert abs(D[0, k, i] - dm) < 2e-7
+            assert abs(D[1, k, i] - 1.0 / E(zz, m)) < 2e-7
