@@ -338,9 +338,12 @@ def main():
         f = wd["fid"]
         kw = dict(newton=wd["newton"], mu=wd["mu"], trust=wd["trust"], rtol=wd["rtol"],
                   atol=wd["atol"], N_start=wd["t0"])
+        # the solver's output nodes are the 64 dense redshifts; the model at the 7 data
+        # redshifts comes from the spline through them
+        kw["N_data"] = wd["N_nodes"]
         K = len(wd["N_nodes"])
         fid = api.de_profile([f["lam"]], [f["om"]], [f["h"]], [1.0 - f["om"] - wd["omega_r"]],
-                             wd["omega_r"], wd["N_nodes"], np.zeros((2, K, 1)), np.ones((2, K)),
+                             wd["omega_r"], wd["N_spline"], np.zeros((2, K, 1)), np.ones((2, K)),
                              iters=0, **kw)
         dfid = fid["dist"][:, :, 0]
         nm, nl = wd["eps"].shape[0], len(wd["lam_grid"])
@@ -353,10 +356,11 @@ def main():
         om0 = torch.full((nfit,), wd["start"]["om"], **dev)
         h0 = torch.full((nfit,), wd["start"]["h"], **dev)
         a00 = 1.0 - om0 - wd["omega_r"]
-        Nn = torch.as_tensor(wd["N_nodes"], **dev)
+        Nn = torch.as_tensor(wd["N_spline"], **dev)
 
         prof = {"workload": f"{nm} mocks x {nl} slopes = {nfit} Gauss-Newton fits, "
-                            f"{wd['iters']} iterations, 7 nodes"}
+                            f"{wd['iters']} iterations, 64 solver nodes, spline to 7 data "
+                            "redshifts"}
         # "a0 supplied": the flat amplitude at the start is handed in and moved to first order
         # with da0/dOm (no shooting in the timed fits)
         a0_flat = api.de_profile(lam, om0, h0, a00, wd["omega_r"], Nn, data, sigma, iters=0,

@@ -242,8 +242,12 @@ gs_status gs_solve_sens(const gs_solve_args* args, const gs_sens_args* sens);
  * and the derivative along flat models from the implicit-function theorem
  * (eq:de-ift); both sensitivities come from the same ensemble solve
  * (gs_solve_sens).  Model distances are D_M = (I(0) - I(N_k)) / h and
- * D_H = 1 / (h E(N_k)) in reference Hubble distances; residuals
- * r = (model - data) / sigma, D_M at every node then D_H.
+ * D_H = 1 / (h E(N_k)) in reference Hubble distances at the K nodes.  With
+ * K_data = 0 the data sit at the nodes; with K_data > 0 the model at the
+ * data e-folds N_data is read off the not-a-knot cubic spline in ln(1+z)
+ * through the node values (appendix "Data model and minimiser"; K >= 4, data
+ * outside the node range use the end intervals).  Residuals
+ * r = (model - data) / sigma, D_M at every data point then D_H.
  *
  * Each iteration: `newton` shooting steps, one solve with both
  * sensitivities at the K nodes, then the update psi <- psi -
@@ -264,8 +268,10 @@ typedef struct gs_de_profile_args {
   double omega_r;           /* radiation density (shared)                   */
   int32_t K;                /* nodes, >= 1                                  */
   const double* N_nodes;    /* [K] e-folds N = -ln(1+z), increasing, <= 0   */
-  const double* data;       /* [2][K][n] D_M then D_H                       */
-  const double* sigma;      /* [2][K]                                       */
+  int32_t K_data;           /* data points; 0: the data sit at the nodes     */
+  const double* N_data;     /* [K_data] e-folds of the data, or NULL         */
+  const double* data;       /* [2][Kd][n] D_M then D_H, Kd = K_data or K     */
+  const double* sigma;      /* [2][Kd]                                      */
   int32_t iters;            /* Gauss-Newton iterations                      */
   int32_t newton;           /* shooting steps per iteration                 */
   double mu;                /* damping of eq:de-gn                          */
@@ -276,7 +282,8 @@ typedef struct gs_de_profile_args {
   double* chi2;             /* [n] out: at the returned parameters          */
   double* chi2_prev;        /* [n] out: before the last update              */
   double* decrement;        /* [n] out: g^T step of the last update         */
-  double* dist;             /* [2][K][n] out: model distances, or NULL      */
+  double* dist;             /* [2][Kd][n] out: model distances at the data,
+                               or NULL                                      */
   int32_t* status;          /* [n] out: worst gs_traj_status of all solves  */
   void* workspace;
   size_t workspace_bytes;

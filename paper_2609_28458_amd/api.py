@@ -77,7 +77,7 @@ class gs_de_profile_args(C.Structure):
     _fields_ = [
         ("n", C.c_int64), ("lambda_", C.c_void_p), ("omega_m", C.c_void_p), ("h", C.c_void_p),
         ("a0", C.c_void_p), ("omega_r", C.c_double), ("K", C.c_int32), ("N_nodes", C.c_void_p),
-        ("data", C.c_void_p), ("sigma", C.c_void_p), ("iters", C.c_int32), ("newton", C.c_int32),
+        ("K_data", C.c_int32), ("N_data", C.c_void_p), ("data", C.c_void_p), ("sigma", C.c_void_p), ("iters", C.c_int32), ("newton", C.c_int32),
         ("mu", C.c_double), ("trust_om", C.c_double), ("trust_h", C.c_double),
         ("tableau", C.c_int32), ("N_start", C.c_double), ("rtol", C.c_double),
         ("atol", C.c_double), ("chi2", C.c_void_p), ("chi2_prev", C.c_void_p),
@@ -382,12 +382,13 @@ def gs_de_profile(args: gs_de_profile_args) -> None:
 
 def de_profile(lam, omega_m, h, a0, omega_r, N_nodes, data, sigma, *, iters=20, newton=3,
                mu=1e-3, trust=(0.05, 0.05), tableau="dopri5", N_start=None, rtol=1.78e-4,
-               atol=1.78e-7, device="cuda", stream=None):
+               atol=1.78e-7, N_data=None, device="cuda", stream=None):
     """Dark-energy profile fits (gs_de_profile): n minimisations at fixed
     lam [n], psi = (omega_m, h) from the given starts, a0 [n] the starting
-    amplitudes; data [2][K][n], sigma [2][K].  Returns a dict of device
-    tensors: omega_m, h, a0, chi2, chi2_prev, decrement, dist [2][K][n],
-    status."""
+    amplitudes; data [2][Kd][n], sigma [2][Kd] at the K nodes (Kd = K) or,
+    with N_data [Kd], at those e-folds through the spline over the nodes.
+    Returns a dict of device tensors: omega_m, h, a0, chi2, chi2_prev,
+    decrement, dist [2][Kd][n], status."""
     f64 = dict(dtype=torch.float64, device=device)
     lam_t = torch.as_tensor(lam, **f64).contiguous()
     n = lam_t.numel()
@@ -396,19 +397,22 @@ def de_profile(lam, omega_m, h, a0, omega_r, N_nodes, data, sigma, *, iters=20, 
            "a0": torch.as_tensor(a0, **f64).clone().contiguous()}
     Nn = torch.as_tensor(N_nodes, **f64).contiguous()
     K = Nn.numel()
+    Nd = None if N_data is None else torch.as_tensor(N_data, **f64).contiguous()
+    Kd = K if Nd is None else Nd.numel()
     data_t = torch.as_tensor(data, **f64).contiguous()
     sig_t = torch.as_tensor(sigma, **f64).contiguous()
-    if tuple(data_t.shape) != (2, K, n) or tuple(sig_t.shape) != (2, K):
-        raise ValueError("data must be [2][K][n] and sigma [2][K]")
+    if tuple(data_t.shape) != (2, Kd, n) or tuple(sig_t.shape) != (2, Kd):
+        raise ValueError("data must be [2][Kd][n] and sigma [2][Kd]")
     for k in ("chi2", "chi2_prev", "decrement"):
         out[k] = torch.empty(n, **f64)
-    out["dist"] = torch.empty((2, K, n), **f64)
+    out["dist"] = torch.empty((2, Kd, n), **f64)
     out["status"] = torch.empty(n, dtype=torch.int32, device=device)
     a = gs_de_profile_args()
     a.n, a.lambda_, a.omega_m, a.h, a.a0 = n, _ptr(lam_t), _ptr(out["omega_m"]), _ptr(out["h"]), \
         _ptr(out["a0"])
     a.omega_r, a.K, a.N_nodes, a.data, a.sigma = float(omega_r), K, _ptr(Nn), _ptr(data_t), \
         _ptr(sig_t)
+    a.K_data, a.N_data = (0, None) if Nd is None else (Kd, _ptr(Nd))
     a.iters, a.newton, a.mu = int(iters), int(newton), float(mu)
     a.trust_om, a.trust_h = float(trust[0]), float(trust[1])
     a.tableau = TABLEAU[tableau] if isinstance(tableau, str) else int(tableau)
@@ -422,7 +426,7 @@ def de_profile(lam, omega_m, h, a0, omega_r, N_nodes, data, sigma, *, iters=20, 
     a.workspace, a.workspace_bytes = ws.data_ptr(), ws.numel()
     a.stream = _stream_handle(stream)
     gs_de_profile(a)
-    out["_keep"] = (lam_t, Nn, data_t, sig_t, ws)
+    out["_keep"] = (lam_t, Nn, Nd, data_t, sig_t, ws)
     return out
 
 

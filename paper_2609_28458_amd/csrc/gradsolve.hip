@@ -370,7 +370,8 @@ void sens_launches(const gs_solve_args* a, const gs_sens_args* sa) {
 // atol), theta [4][n], y0 [3][n], y_out [3][K][n], y_final [3][n],
 // S_out [3][2][K][n], S_final [3][2][n], and three int32 [n] arrays.
 struct DeLayout {
-  size_t counters, scal, theta, y0, y_out, y_final, S_out, S_final, nacc, nrej, st, total;
+  size_t counters, scal, theta, y0, y_out, y_final, S_out, S_final, nacc, nrej, st;
+  size_t W, tmp, node, total;  // spline only: weights, their scratch, node values
 };
 DeLayout de_layout(const gs_de_profile_args* A) {
   DeLayout L;
@@ -392,6 +393,10 @@ DeLayout de_layout(const gs_de_profile_args* A) {
   L.nacc = take(n * 4);
   L.nrej = take(n * 4);
   L.st = take(n * 4);
+  const size_t Kd = A->K_data > 0 ? (size_t)A->K_data : 0;
+  L.W = take(Kd * K * 8);
+  L.tmp = take(Kd ? 3 * K * K * 8 : 0);
+  L.node = take(Kd ? 4 * K * n * 8 : 0);
   L.total = off;
   return L;
 }
@@ -423,12 +428,14 @@ gs_status gs_solve_sens(const gs_solve_args* a, const gs_sens_args* sa) {
 }
 
 size_t gs_de_profile_workspace_bytes(const gs_de_profile_args* A) {
-  if (!A || A->n < 0 || A->K < 1) return 0;
+  if (!A || A->n < 0 || A->K < 1 || A->K_data < 0) return 0;
   return de_layout(A).total;
 }
 
 gs_status gs_de_profile(const gs_de_profile_args* A) {
-  if (!A || A->n < 0 || A->K < 1 || A->iters < 0 || A->newton < 0) return GS_ERR_INVALID;
+  if (!A || A->n < 0 || A->K < 1 || A->iters < 0 || A->newton < 0 || A->K_data < 0)
+    return GS_ERR_INVALID;
+  if (A->K_data > 0 && (A->K < 4 || !A->N_data)) return GS_ERR_INVALID;
   if (A->tableau < 0 || A->tableau >= kNumTab || !(A->rtol > 0.0) || !(A->atol >= 0.0) ||
       !(A->N_start < 0.0) || !(A->mu >= 0.0) || !(A->trust_om > 0.0) || !(A->trust_h > 0.0))
     return GS_ERR_INVALID;
@@ -499,6 +506,15 @@ gs_status gs_de_profile(const gs_de_profile_args* A) {
   g.S_final = D(L.S_final);
   g.data = A->data;
   g.sigma = A->sigma;
+  g.Kd = A->K_data > 0 ? A->K_data : A->K;
+  g.W = nullptr;
+  g.node = nullptr;
+  if (A->K_data > 0) {
+    hipLaunchKernelGGL(gs::de::spline_weights_kernel, dim3((A->K + 63) / 64), dim3(64), 0, s,
+                       A->K, A->N_nodes, A->K_data, A->N_data, D(L.tmp), D(L.W));
+    g.W = D(L.W);
+    g.node = D(L.node);
+  }
   g.status = I(L.st);
   g.mu = A->mu;
   g.trust_om = A->trust_om;

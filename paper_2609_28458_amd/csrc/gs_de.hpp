@@ -10,6 +10,11 @@
 //   distances         D_M = (I(0) - I(N_z)) / h, D_H = 1/(h E(N_z))
 //   damped GN         psi <- psi - (J^T J + mu diag J^T J)^{-1} J^T r,
 //                     psi = (Om, h), r = (D - data)/sigma        eq:de-gn
+// Optionally the model distances at the data redshifts are read off a cubic
+// spline through the node values (appendix "Data model and minimiser"): the
+// not-a-knot spline in ln(1+z), built here in N = -ln(1+z) (an affine change
+// of variable maps the one spline onto the other), applied as a fixed matrix
+// W [Kd][K] to the node values and to their derivatives.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -69,6 +74,61 @@ __global__ void shoot_kernel(int64_t n, double* theta, const double* y_final,
   status_out[i] = max(status_out[i], status[i]);
 }
 
+// Spline weights: thread c interpolates the unit vector e_c.  Slopes s_i of
+// the Hermite form solve the tridiagonal system of a C2 cubic spline, with
+// the not-a-knot conditions (third derivative continuous at the second and
+// the next-to-last node) folded into the first and last rows; Thomas
+// elimination.  Data outside the node range use the end intervals.  K >= 4,
+// u strictly increasing; tmp holds 3 K doubles per thread.
+__global__ void spline_weights_kernel(int32_t K, const double* u, int32_t Kd, const double* ud,
+                                      double* tmp, double* W) {
+  const int c = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+  if (c >= K) return;
+  double* cp = tmp + (size_t)c * 3 * K;
+  double* rp = cp + K;
+  double* s = rp + K;
+  auto hh = [&](int i) { return u[i + 1] - u[i]; };
+  auto yv = [&](int i) { return i == c ? 1.0 : 0.0; };
+  auto dl = [&](int i) { return (yv(i + 1) - yv(i)) / hh(i); };
+  for (int i = 0; i < K; ++i) {
+    double a, b, cc, r;
+    if (i == 0) {
+      const double h0 = hh(0), h1 = hh(1);
+      a = 0.0;
+      b = h1;
+      cc = h0 + h1;
+      r = ((3.0 * h0 + 2.0 * h1) * h1 * dl(0) + h0 * h0 * dl(1)) / (h0 + h1);
+    } else if (i == K - 1) {
+      const double hl = hh(K - 2), hm = hh(K - 3);
+      a = hl + hm;
+      b = hm;
+      cc = 0.0;
+      r = (hl * hl * dl(K - 3) + (3.0 * hl + 2.0 * hm) * hm * dl(K - 2)) / (hm + hl);
+    } else {
+      const double hm = hh(i - 1), hi = hh(i);
+      a = hi;
+      b = 2.0 * (hm + hi);
+      cc = hm;
+      r = 3.0 * (hi * dl(i - 1) + hm * dl(i));
+    }
+    const double m = i == 0 ? b : b - a * cp[i - 1];
+    cp[i] = cc / m;
+    rp[i] = i == 0 ? r / m : (r - a * rp[i - 1]) / m;
+  }
+  s[K - 1] = rp[K - 1];
+  for (int i = K - 2; i >= 0; --i) s[i] = rp[i] - cp[i] * s[i + 1];
+  for (int q = 0; q < Kd; ++q) {
+    const double x = ud[q];
+    int i = 0;
+    while (i < K - 2 && x > u[i + 1]) ++i;
+    const double h = hh(i);
+    const double tt = (x - u[i]) / h;
+    const double t2 = tt * tt, t3 = t2 * tt;
+    W[(size_t)q * K + c] = yv(i) * (2.0 * t3 - 3.0 * t2 + 1.0) + h * s[i] * (t3 - 2.0 * t2 + tt) +
+                           yv(i + 1) * (3.0 * t2 - 2.0 * t3) + h * s[i + 1] * (t3 - t2);
+  }
+}
+
 // Residuals, Jacobian along flat models and (update != 0) the damped
 // Gauss-Newton step of every minimisation.  S_* are [3][2][*][n] with
 // column 0 = d/da0 and column 1 = d/dOm.
@@ -80,8 +140,11 @@ struct GnArgs {
   const double* y_final;  // [3][n]
   const double* S_out;    // [3][2][K][n]
   const double* S_final;  // [3][2][n]
-  const double* data;     // [2][K][n]
-  const double* sigma;    // [2][K]
+  const double* data;     // [2][Kd][n]
+  const double* sigma;    // [2][Kd]
+  int32_t Kd;             // data points (= K without spline)
+  const double* W;        // [Kd][K] spline weights, or null: data at the nodes
+  double* node;           // [4][K][n] node values (D_M, D_H, dD_M/dOm, dD_H/dOm) with W
   const int32_t* status;  // [n] of the solve
   double mu, trust_om, trust_h;
   int32_t update;
@@ -90,7 +153,7 @@ struct GnArgs {
   double* chi2;           // [n] chi2 at the input parameters
   double* chi2_prev;      // [n] (update) chi2 before this step
   double* decrement;      // [n] (update) g^T step
-  double* dist;           // [2][K][n] model distances, or null
+  double* dist;           // [2][Kd][n] model distances at the data, or null
   int32_t* status_out;    // [n] worst solver status
 };
 
@@ -114,10 +177,11 @@ __global__ void gn_kernel(GnArgs A) {
   const double da0 = -dg_om / dg_a0;
   const double dI0 = Sf(2, 1) + da0 * Sf(2, 0);
   double A11 = 0.0, A12 = 0.0, A22 = 0.0, g1 = 0.0, g2 = 0.0, chi2 = 0.0;
-  auto add = [&](double D, double dDo, double dDh, double data, double sig, int q, int k) {
-    if (A.dist) A.dist[((int64_t)q * A.K + k) * n + i] = D;
-    const double r = (D - data) / sig;
-    const double j1 = dDo / sig, j2 = dDh / sig;
+  auto add = [&](double D, double dDo, int q, int j) {
+    if (A.dist) A.dist[((int64_t)q * A.Kd + j) * n + i] = D;
+    const double sig = A.sigma[q * A.Kd + j];
+    const double r = (D - A.data[((int64_t)q * A.Kd + j) * n + i]) / sig;
+    const double j1 = dDo / sig, j2 = (-D / h) / sig;  // distances scale as 1/h
     A11 += j1 * j1;
     A12 += j1 * j2;
     A22 += j2 * j2;
@@ -125,24 +189,56 @@ __global__ void gn_kernel(GnArgs A) {
     g2 += j2 * r;
     chi2 += r * r;
   };
-  // D_M at every node, then D_H (the order of the residual vector)
-  for (int k = 0; k < A.K; ++k) {
+  // D_M and D_H at node k with their derivatives along flat models
+  auto node_dm = [&](int k, double& dDo) {
     const double Ik = A.y_out[((int64_t)2 * A.K + k) * n + i];
     const double dIk = So(2, 1, k) + da0 * So(2, 0, k);
-    const double DM = (I0 - Ik) / h;
-    add(DM, (dI0 - dIk) / h, -DM / h, A.data[(int64_t)k * n + i], A.sigma[k], 0, k);
-  }
-  for (int k = 0; k < A.K; ++k) {
+    dDo = (dI0 - dIk) / h;
+    return (I0 - Ik) / h;
+  };
+  auto node_dh = [&](int k, double& dDo) {
     const double N = A.N_nodes[k];
     const double phi = A.y_out[(int64_t)k * n + i], u = A.y_out[((int64_t)A.K + k) * n + i];
     const E2 e = e2_at(N, phi, u, a0, lam, om, orad);
     const double E = sqrt(e.nm / e.dn);
-    const double DH = 1.0 / (h * E);
     const double dphi = So(0, 1, k) + da0 * So(0, 0, k);
     const double du = So(1, 1, k) + da0 * So(1, 0, k);
     const double dE2 = de2(e, N, u, a0, lam, dphi, du, da0, 1.0);
-    add(DH, -0.5 * dE2 / (h * E * E * E), -DH / h, A.data[((int64_t)A.K + k) * n + i],
-        A.sigma[A.K + k], 1, k);
+    dDo = -0.5 * dE2 / (h * E * E * E);
+    return 1.0 / (h * E);
+  };
+  // D_M at every data point, then D_H (the order of the residual vector)
+  if (!A.W) {
+    for (int k = 0; k < A.K; ++k) {
+      double d;
+      const double D = node_dm(k, d);
+      add(D, d, 0, k);
+    }
+    for (int k = 0; k < A.K; ++k) {
+      double d;
+      const double D = node_dh(k, d);
+      add(D, d, 1, k);
+    }
+  } else {
+    const int64_t KN = (int64_t)A.K * n;
+    for (int k = 0; k < A.K; ++k) {
+      double d0, d1;
+      A.node[k * n + i] = node_dm(k, d0);
+      A.node[KN + k * n + i] = node_dh(k, d1);
+      A.node[2 * KN + k * n + i] = d0;
+      A.node[3 * KN + k * n + i] = d1;
+    }
+    for (int q = 0; q < 2; ++q) {
+      for (int j = 0; j < A.Kd; ++j) {
+        const double* w = A.W + (int64_t)j * A.K;
+        double D = 0.0, d = 0.0;
+        for (int k = 0; k < A.K; ++k) {
+          D = fma(w[k], A.node[q * KN + k * n + i], D);
+          d = fma(w[k], A.node[(2 + q) * KN + k * n + i], d);
+        }
+        add(D, d, q, j);
+      }
+    }
   }
   A.chi2[i] = chi2;
   A.status_out[i] = max(A.status_out[i], A.status[i]);

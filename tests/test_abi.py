@@ -114,3 +114,39 @@ def test_sens_argument_checks():
     # no tape and no wide groups with sensitivities
     assert api.lib().gs_solve_sens(C.byref(_args(ckpt_every=4, ckpt_capacity=10)), C.byref(ok)) == 2
     assert api.lib().gs_solve_sens(C.byref(_args(wide=8)), C.byref(ok)) == 2
+
+
+def _de_args(**kw):
+    a = api.gs_de_profile_args()
+    a.n, a.K, a.K_data = 1000, 64, 7
+    for f in ("lambda_", "omega_m", "h", "a0", "N_nodes", "N_data", "data", "sigma", "chi2",
+              "chi2_prev", "decrement", "status"):
+        setattr(a, f, 0x1000)
+    a.iters, a.newton, a.mu, a.trust_om, a.trust_h = 20, 3, 1e-3, 0.05, 0.05
+    a.tableau, a.N_start, a.rtol, a.atol = 0, -3.9, 1.78e-4, 1.78e-7
+    a.workspace = 0x100000
+    for k, v in kw.items():
+        setattr(a, k, v)
+    return a
+
+
+def _al(x):
+    return (x + 255) // 256 * 256
+
+
+def test_de_profile_workspace_and_argument_checks():
+    L = api.lib()
+    n, K, Kd = 1000, 64, 7
+    direct = sum(_al(b) for b in (256, 32, 4 * n * 8, 3 * n * 8, 3 * K * n * 8, 3 * n * 8,
+                                  6 * K * n * 8, 6 * n * 8, 4 * n, 4 * n, 4 * n, 0, 0, 0))
+    spline = direct + _al(Kd * K * 8) + _al(3 * K * K * 8) + _al(4 * K * n * 8)
+    assert L.gs_de_profile_workspace_bytes(C.byref(_de_args(K_data=0))) == direct
+    assert L.gs_de_profile_workspace_bytes(C.byref(_de_args())) == spline
+    assert L.gs_de_profile_workspace_bytes(C.byref(_de_args(K_data=-1))) == 0
+    assert L.gs_de_profile(C.byref(_de_args(workspace_bytes=spline - 1))) == 3
+    assert L.gs_de_profile(C.byref(_de_args(workspace=0x100001, workspace_bytes=spline))) == 3
+    for bad in (dict(K_data=-1), dict(K=3), dict(N_data=None), dict(iters=-1), dict(newton=-1),
+                dict(N_start=0.0), dict(trust_h=0.0), dict(tableau=3), dict(data=None)):
+        assert L.gs_de_profile(C.byref(_de_args(workspace_bytes=spline, **bad))) == 1, bad
+    # n = 0 is a no-op, whatever the pointers
+    assert L.gs_de_profile(C.byref(_de_args(n=0, workspace=None))) == 0

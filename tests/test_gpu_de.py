@@ -20,13 +20,18 @@ def _gpu():
     api.lib()
 
 
-def _setup(de, n_mocks, n_lambda):
+def _setup(de, n_mocks, n_lambda, spline=False):
+    """Mock fits; with spline the solver's nodes are the 64 dense nodes and
+    the data sit at the 7 data redshifts (w["nodes"], w["N_data"])."""
     w = inputs.de_profile_mocks(n_mocks=n_mocks, n_lambda=n_lambda)
+    w["N_data"] = w["N_nodes"] if spline else None
+    w["nodes"] = w["N_spline"] if spline else w["N_nodes"]
     s = dict(tableau=w["tableau"], t0=w["t0"], rtol=w["rtol"], atol=w["atol"])
     f, orad = w["fid"], w["omega_r"]
     lam1, om1 = np.array([f["lam"]]), np.array([f["om"]])
     a0f = de.flat_amplitude(1.0 - om1 - orad, lam1, om1, orad, s, 4)
-    Dfid = de.model(a0f, lam1, om1, np.array([f["h"]]), orad, w["N_nodes"], s)[0][:, :, 0]
+    Dfid = de.at_data(de.model(a0f, lam1, om1, np.array([f["h"]]), orad, w["nodes"], s)[0],
+                      w["nodes"], w["N_data"])[:, :, 0]
     n = n_mocks * n_lambda
     mock = np.arange(n) // n_lambda
     lam = w["lam_grid"][np.arange(n) % n_lambda]
@@ -37,19 +42,26 @@ def _setup(de, n_mocks, n_lambda):
 
 
 def _run_gpu(w, lam, om, h, a0, data, sigma, **kw):
-    out = api.de_profile(lam, om, h, a0, w["omega_r"], w["N_nodes"], data, sigma,
+    out = api.de_profile(lam, om, h, a0, w["omega_r"], w["nodes"], data, sigma,
                          iters=kw.get("iters", w["iters"]), newton=w["newton"], mu=w["mu"],
-                         trust=w["trust"], rtol=w["rtol"], atol=w["atol"], N_start=w["t0"])
+                         trust=w["trust"], rtol=w["rtol"], atol=w["atol"], N_start=w["t0"],
+                         N_data=w["N_data"])
     torch.cuda.synchronize()
     return {k: v.cpu().numpy() for k, v in out.items() if k != "_keep"}
 
 
-def test_profile_matches_oracle(orc):
+def _oracle(de, w, s, lam, om, h, a0, data, sigma):
+    return de.profile(lam, om, h, a0, w["omega_r"], w["nodes"], data, sigma, s,
+                      iters=w["iters"], newton=w["newton"], mu=w["mu"], trust=w["trust"],
+                      N_data=w["N_data"])
+
+
+@pytest.mark.parametrize("spline", [False, True], ids=["data_at_nodes", "spline_64"])
+def test_profile_matches_oracle(orc, spline):
     from oracle import de_profile as de
-    w, s, lam, om, h, a0, data, sigma = _setup(de, 2, 6)
+    w, s, lam, om, h, a0, data, sigma = _setup(de, 2, 6, spline)
     g = _run_gpu(w, lam, om, h, a0, data, sigma)
-    o = de.profile(lam, om, h, a0, w["omega_r"], w["N_nodes"], data, sigma, s,
-                   iters=w["iters"], newton=w["newton"], mu=w["mu"], trust=w["trust"])
+    o = _oracle(de, w, s, lam, om, h, a0, data, sigma)
     assert np.all(g["status"] == 0)
     for k in ("om", "h", "a0"):
         gk = g["omega_m" if k == "om" else k]
@@ -69,14 +81,28 @@ def test_profile_recovers_noise_free_fiducial(orc):
     assert g["chi2"][0] < 1e-10
 
 
-def test_profile_full_size(orc):
+def test_spline_with_data_at_nodes_equals_direct(orc):
+    """Data redshifts among the spline nodes: the spline returns the node
+    values, so the fits equal those with the nodes at the data."""
+    from oracle import de_profile as de
+    w, s, lam, om, h, a0, data, sigma = _setup(de, 2, 5)
+    a = _run_gpu(w, lam, om, h, a0, data, sigma)
+    w["nodes"] = np.unique(np.concatenate([w["N_nodes"], w["N_spline"]]))
+    w["N_data"] = w["N_nodes"]
+    b = _run_gpu(w, lam, om, h, a0, data, sigma)
+    for k in ("omega_m", "h", "a0", "chi2", "dist"):
+        np.testing.assert_allclose(b[k], a[k], rtol=1e-12, atol=1e-14, err_msg=k)
+
+
+@pytest.mark.parametrize("spline", [False, True], ids=["data_at_nodes", "spline_64"])
+def test_profile_full_size(orc, spline):
     """100 mocks x 100 slopes = 10^4 minimisations of 20 iterations: every
     fit passes the convergence test of the paper (|dchi2| < 1e-4 over the
     last step, decrement below 1e-6) or is reported, the profile minimum
     of every mock is near the fiducial slope, and 12 sampled fits equal the
     oracle's."""
     from oracle import de_profile as de
-    w, s, lam, om, h, a0, data, sigma = _setup(de, 100, 100)
+    w, s, lam, om, h, a0, data, sigma = _setup(de, 100, 100, spline)
     g = _run_gpu(w, lam, om, h, a0, data, sigma)
     assert np.all(g["status"] == 0)
     conv = (np.abs(g["chi2_prev"] - g["chi2"]) < 1e-4) & (np.abs(g["decrement"]) < 1e-6)
@@ -87,9 +113,7 @@ def test_profile_full_size(orc):
     print(f"best-fit slope over mocks: median {np.median(best):.3f}")
     assert abs(np.median(best) - w["fid"]["lam"]) < 0.3
     idx = np.random.default_rng(4).choice(10_000, 12, replace=False)
-    o = de.profile(lam[idx], om[idx], h[idx], a0[idx], w["omega_r"], w["N_nodes"],
-                   data[:, :, idx], sigma, s, iters=w["iters"], newton=w["newton"], mu=w["mu"],
-                   trust=w["trust"])
+    o = _oracle(de, w, s, lam[idx], om[idx], h[idx], a0[idx], data[:, :, idx], sigma)
     np.testing.assert_allclose(g["omega_m"][idx], o["om"], rtol=1e-9)
     np.testing.assert_allclose(g["h"][idx], o["h"], rtol=1e-9)
     np.testing.assert_allclose(g["chi2"][idx], o["chi2"], rtol=1e-7, atol=1e-9)
