@@ -2,7 +2,9 @@
 
 A plain, slow FP64 CPU reference for the adaptive explicit Runge--Kutta
 ensemble solve of the paper (Appendix "Numerical details": eq:rk,
-eq:errnorm, eq:controller, eq:dense, eq:stage-sens).  It is loaded only by
+eq:errnorm, eq:controller, eq:dense, eq:stage-sens), and for the stiff path:
+a Rosenbrock solve (Rodas4 in the textbook form) of stiff kinetics networks
+(``stiff.cpp``).  It is loaded only by
 the test suite, the smoke check and the CPU-baseline leg of the benchmark; the
 product library never imports it and shares no source with it.
 
@@ -19,12 +21,14 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libgso.so")
-SOURCES = ["solver.cpp", "tableaux.cpp"]
+SOURCES = ["solver.cpp", "tableaux.cpp", "stiff.cpp"]
 
-RHS = {"harmonic": 0, "kepler": 1, "loghalo": 2, "spinprec": 3, "quint": 4}
-DIM = {0: 2, 1: 4, 2: 6, 3: 9, 4: 3}
-NPARAM = {0: 1, 1: 1, 2: 3, 3: 3, 4: 4}
-TABLEAU = {"dopri5": 0, "tsit5": 1, "verner7": 2}
+RHS = {"harmonic": 0, "kepler": 1, "loghalo": 2, "spinprec": 3, "quint": 4, "kin3": 5,
+       "kin8": 6}
+DIM = {0: 2, 1: 4, 2: 6, 3: 9, 4: 3, 5: 3, 6: 8}
+NPARAM = {0: 1, 1: 1, 2: 3, 3: 3, 4: 4, 5: 3, 6: 12}
+TABLEAU = {"dopri5": 0, "tsit5": 1, "verner7": 2, "rodas4": 3}
+STIFF_RHS = (5, 6)
 STATUS = {0: "OK", 1: "MAX_STEPS", 2: "DT_UNDERFLOW", 3: "NONFINITE"}
 
 
@@ -75,6 +79,12 @@ def lib():
         _lib.gso_tableau.argtypes = [C.c_int, C.c_void_p, C.c_void_p]
         _lib.gso_rhs.argtypes = [C.c_int, C.c_double, C.c_void_p, C.c_void_p, C.c_int32,
                                  C.c_void_p, C.c_void_p, C.c_void_p]
+        _lib.gso_stiff_solve.argtypes = [C.POINTER(_Problem)]
+        _lib.gso_stiff_solve.restype = C.c_int
+        _lib.gso_stiff_rhs.argtypes = [C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
+        _lib.gso_stiff_rhs.restype = C.c_int
+        _lib.gso_rodas4.argtypes = [C.c_void_p]
+        _lib.gso_rodas4.restype = C.c_int
     return _lib
 
 
@@ -178,7 +188,8 @@ def solve(rhs, tableau, y0, theta, t0, t1, rtol, atol, t_out=None, *, max_steps=
     P.nthreads = nthreads or min(os.cpu_count() or 1, 16)
     P.m, P.cols, P.S_out, P.S_final = m, _ptr(cols), _ptr(S_out), _ptr(S_final)
     P.h_cap, P.h_rec, P.h_replay, P.n_replay = int(h_cap), _ptr(h_rec), _ptr(hr), _ptr(nr)
-    rc = lib().gso_solve(C.byref(P))
+    stiff = rhs_id in STIFF_RHS or tab_id == TABLEAU["rodas4"]
+    rc = (lib().gso_stiff_solve if stiff else lib().gso_solve)(C.byref(P))
     if rc != 0:
         raise ValueError(f"gso_solve rejected the problem (code {rc})")
     if K:
@@ -225,3 +236,25 @@ def rhs(name, t, y, theta, sens_cols=None):
     if rc != 0:
         raise ValueError("gso_rhs")
     return (f, J[:, :m]) if m else f
+
+
+def stiff_rhs(name, y, theta):
+    """f and the analytic Jacobian [d][d] of a stiff kinetics right-hand side."""
+    rid = RHS[name] if isinstance(name, str) else int(name)
+    d = DIM[rid]
+    y, theta = _f64(y), _f64(theta)
+    f = np.zeros(d)
+    J = np.zeros((d, d))
+    if lib().gso_stiff_rhs(rid, y.ctypes.data, theta.ctypes.data, f.ctypes.data,
+                           J.ctypes.data) != 0:
+        raise ValueError("gso_stiff_rhs")
+    return f, J
+
+
+def rodas4():
+    """Standard-form Rodas4 coefficients derived by the oracle: gamma, alpha,
+    Gamma (lower triangular, diagonal gamma), b, bhat."""
+    out = np.zeros(1 + 36 + 36 + 12)
+    lib().gso_rodas4(out.ctypes.data)
+    return {"gamma": out[0], "alpha": out[1:37].reshape(6, 6), "Gamma": out[37:73].reshape(6, 6),
+            "b": out[73:79], "bhat": out[79:85]}

@@ -16,7 +16,7 @@ constexpr int MAXS = 10;  // most stages of any tableau (Verner 7)
 constexpr int MAXD = 9;   // largest state (spin precession)
 constexpr int MAXP = 4;   // most parameters (quintessence)
 
-enum TableauId { DOPRI5 = 0, TSIT5 = 1, VERNER7 = 2 };
+enum TableauId { DOPRI5 = 0, TSIT5 = 1, VERNER7 = 2, RODAS4 = 3 };
 enum DenseKind { DENSE_POLY = 0, DENSE_SHORT_STEP = 1 };
 
 struct Tableau {
@@ -34,7 +34,8 @@ struct Tableau {
 
 const Tableau& tableau(int id);
 
-enum RhsId { RHS_HARMONIC = 0, RHS_KEPLER = 1, RHS_LOGHALO = 2, RHS_SPINPREC = 3, RHS_QUINT = 4 };
+enum RhsId { RHS_HARMONIC = 0, RHS_KEPLER = 1, RHS_LOGHALO = 2, RHS_SPINPREC = 3, RHS_QUINT = 4,
+             RHS_KIN3 = 5, RHS_KIN8 = 6 };  // the last two: stiff kinetics, Rodas4 only
 int rhs_dim(int id);     // d
 int rhs_nparam(int id);  // p
 
@@ -101,4 +102,12 @@ int gso_tableau(int id, int32_t* ints, double* dbl);
 // d f / d z_c for the same column convention as gso_problem (J [d][m]).
 int gso_rhs(int rhs, double t, const double* y, const double* theta, int32_t m,
             const int32_t* cols, double* f, double* J);
+
+// Stiff path (stiff.cpp): Rosenbrock solve of an ensemble of RHS_KIN3 /
+// RHS_KIN8 problems with tableau RODAS4 (no sensitivities, no replay);
+// outputs are landed on.  f and analytic Jacobian J [d][d] of those
+// right-hand sides; standard-form Rodas4 coefficients.
+int gso_stiff_solve(const gso_problem* p);
+int gso_stiff_rhs(int rhs, const double* y, const double* theta, double* f, double* J);
+int gso_rodas4(double* out);
 }

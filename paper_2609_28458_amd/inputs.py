@@ -151,3 +151,45 @@ def de_profile_mocks(n_mocks=100, n_lambda=100, seed=6, omega_r=9.0e-5):
                 N_spline=qd["t_out"], t0=q["t0"],
                 tableau="dopri5", rtol=q["rtol"], atol=q["atol"], iters=20, newton=3,
                 mu=1e-3, trust=(0.05, 0.05))
+
+
+def _logu(rng, lo, hi, n):
+    return np.exp(rng.uniform(np.log(lo), np.log(hi), n))
+
+
+# Nominal rates of the eight-species network (k1..k10, source s, k12).
+KIN8_NOMINAL = np.array([1.0, 0.5, 10.0, 0.1, 5.0, 3.0e3, 100.0, 1.0, 100.0, 0.01, 1.0e-3, 1.0])
+
+
+def kinetics3(n=100_000, seed=7, K=16):
+    """Stiff three-species autocatalytic kinetics (a -> b, b + c -> 2c,
+    c -> a), a stand-in for the classic stiff chemistry problems: rates
+    k1 ~ logU[1e-2, 1e-1], k2 ~ logU[1e6, 1e7], k3 ~ logU[0.1, 1], so the fast
+    and slow time-scales differ by 7-9 decades; start (1 - c0, 0, c0),
+    c0 ~ logU[1e-4, 1e-2]; spans t1 ~ logU[10, 1e4]; Rodas4 at rtol 1e-6,
+    atol 1e-10; K output times per trajectory, log-spaced from t1 1e-6 to t1."""
+    rng = _rng(seed)
+    k = np.stack([_logu(rng, 1e-2, 1e-1, n), _logu(rng, 1e6, 1e7, n), _logu(rng, 0.1, 1.0, n)])
+    c0 = _logu(rng, 1e-4, 1e-2, n)
+    y0 = np.stack([1.0 - c0, np.zeros(n), c0])
+    t1 = _logu(rng, 10.0, 1e4, n)
+    t_out = t1[None, :] * np.logspace(-6, 0, K)[:, None] if K else None
+    return dict(rhs="kin3", tableau="rodas4", y0=y0, theta=k, t0=0.0, t1=t1, rtol=1e-6,
+                atol=1e-10, t_out=t_out)
+
+
+def kinetics8(n=100_000, seed=8, K=16):
+    """Stiff eight-species network with one reversible bilinear step (see the
+    kin8 right-hand side): every rate its nominal value (KIN8_NOMINAL) times
+    logU[1/3, 3], so the time-scales span about five decades; start y1 = 1,
+    y5 = 1e-3, the rest 0; spans t1 ~ logU[100, 1000]; Rodas4 at rtol 1e-6,
+    atol 1e-10; K output times log-spaced from t1 1e-6 to t1."""
+    rng = _rng(seed)
+    k = KIN8_NOMINAL[:, None] * _logu(rng, 1.0 / 3.0, 3.0, 12 * n).reshape(12, n)
+    y0 = np.zeros((8, n))
+    y0[0] = 1.0
+    y0[4] = 1e-3
+    t1 = _logu(rng, 100.0, 1000.0, n)
+    t_out = t1[None, :] * np.logspace(-6, 0, K)[:, None] if K else None
+    return dict(rhs="kin8", tableau="rodas4", y0=y0, theta=k, t0=0.0, t1=t1, rtol=1e-6,
+                atol=1e-10, t_out=t_out)
