@@ -63,7 +63,12 @@ typedef enum gs_traj_status {
 typedef enum gs_tableau_id {
   GS_DOPRI5 = 0,  /* Dormand & Prince 5(4), FSAL, 4th-order continuous output */
   GS_TSIT5 = 1,   /* Tsitouras 5(4), FSAL, 4th-order interpolant              */
-  GS_VERNER7 = 2  /* Verner 7(6), 10 stages, outputs by shortened steps       */
+  GS_VERNER7 = 2, /* Verner 7(6), 10 stages, outputs by shortened steps       */
+  GS_RODAS4 = 3   /* stiff path: Rosenbrock method Rodas4 (Hairer & Wanner;
+                     order 4, embedded 3, stiffly accurate) with the
+                     analytic Jacobian, for the stiff right-hand sides only;
+                     outputs are landed on (the step is shortened to end at
+                     each output time) instead of interpolated             */
 } gs_tableau_id;
 
 /* Right-hand sides; each fixes d (state size) and p (parameter count). */
@@ -74,8 +79,15 @@ typedef enum gs_rhs_id {
   GS_RHS_SPINPREC = 3, /* d=9 (L, S1, S2 unit vectors) in v, p=3 (q, chi1,
                           chi2); eq:prec-spins, eq:prec-L, eq:prec-omega,
                           eq:prec-rr with 2PN radiation reaction              */
-  GS_RHS_QUINT = 4     /* d=3 (phi, u, I) in N = ln a, p=4 (a0, lambda,
+  GS_RHS_QUINT = 4,    /* d=3 (phi, u, I) in N = ln a, p=4 (a0, lambda,
                           Omega_m, Omega_r); eq:de-model, eq:de-rhs          */
+  /* Stiff mass-action kinetics, autonomous, GS_RODAS4 only: */
+  GS_RHS_KIN3 = 5,     /* d=3 (a, b, c), p=3 (k1, k2, k3): a -> b (k1 a),
+                          b + c -> 2c (k2 b c), c -> a (k3 c)               */
+  GS_RHS_KIN8 = 6      /* d=8, p=12 (k1..k10, s, k12): y1 <-> y2 (k1, k2),
+                          y2 -> y3 (k3), y3 <-> y4 (k4, k5), y4 + y5 <-> y6
+                          (k6 y4 y5, k7 y6), y6 -> y7 (k8), y7 -> y8 (k9),
+                          y8 -> y1 (k10), source s -> y5, y5 -> sink (k12) */
 } gs_rhs_id;
 
 /* How trajectories are handed to lanes. */
@@ -200,7 +212,19 @@ size_t gs_workspace_bytes(const gs_solve_args* args);
 
 /* Integrate every trajectory from t0 to t1 (eq:rk .. eq:dense), writing
  * y_out at the nodes, y_final, step counts and status, and, when
- * ckpt_every > 0, the checkpoint tape into the workspace. */
+ * ckpt_every > 0, the checkpoint tape into the workspace.
+ *
+ * Stiff path (tableau GS_RODAS4 with GS_RHS_KIN3 or GS_RHS_KIN8): the
+ * Rosenbrock kernel for stiff systems that the paper's library pairs with
+ * its explicit kernels (Section "Adaptive explicit Runge--Kutta methods").
+ * Each attempt factors (1/(h gamma) I - J) once (LU, partial pivoting) and
+ * solves six stages in the method's transformed variables; step control as
+ * eq:errnorm / eq:controller with nu = 4 (I control only: beta1 <= 0,
+ * beta2 = 0); an attempt whose matrix has a zero or non-finite pivot counts
+ * as a NaN error norm.  Not available there (GS_ERR_UNSUPPORTED): a tape,
+ * wide groups, gs_solve_vjp, gs_solve_sens, gs_dense_eval.  An explicit
+ * tableau with a stiff right-hand side, or GS_RODAS4 with another one, is
+ * GS_ERR_UNSUPPORTED as well. */
 gs_status gs_solve(const gs_solve_args* args);
 
 /* Reverse-mode derivative of the discrete solution of the last gs_solve call
@@ -302,7 +326,8 @@ gs_status gs_dense_eval(const gs_solve_args* fwd, int32_t Q, const double* t_que
 /* Evaluate the right-hand side and its vector-Jacobian product at m points:
  * f = f(t, y, theta) and, for kbar given, ybar = J_y^T kbar,
  * thetabar = J_theta^T kbar.  y, f, ybar, kbar [d][m]; theta, thetabar [p][m];
- * t [m].  ybar, thetabar, kbar may all be NULL. */
+ * t [m].  ybar, thetabar, kbar may all be NULL.  For the stiff right-hand
+ * sides only f is available (a VJP request is GS_ERR_UNSUPPORTED). */
 gs_status gs_rhs_eval(int32_t rhs, int64_t m, const double* t, const double* y,
                       const double* theta, double* f, const double* kbar, double* ybar,
                       double* thetabar, void* stream);

@@ -22,10 +22,11 @@ import torch
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libgradsolve.so")
 
-RHS = {"harmonic": 0, "kepler": 1, "loghalo": 2, "spinprec": 3, "quint": 4}
-DIM = {0: 2, 1: 4, 2: 6, 3: 9, 4: 3}
-NPARAM = {0: 1, 1: 1, 2: 3, 3: 3, 4: 4}
-TABLEAU = {"dopri5": 0, "tsit5": 1, "verner7": 2}
+RHS = {"harmonic": 0, "kepler": 1, "loghalo": 2, "spinprec": 3, "quint": 4, "kin3": 5,
+       "kin8": 6}
+DIM = {0: 2, 1: 4, 2: 6, 3: 9, 4: 3, 5: 3, 6: 8}
+NPARAM = {0: 1, 1: 1, 2: 3, 3: 3, 4: 4, 5: 3, 6: 12}
+TABLEAU = {"dopri5": 0, "tsit5": 1, "verner7": 2, "rodas4": 3}
 SCHEDULE = {"queue": 0, "static": 1}
 TRAJ_STATUS = {0: "OK", 1: "MAX_STEPS", 2: "DT_UNDERFLOW", 3: "NONFINITE",
                4: "TAPE_OVERFLOW", 5: "BAD_INPUT"}

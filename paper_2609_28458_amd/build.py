@@ -13,10 +13,10 @@ LIB = os.path.join(HERE, "libgradsolve.so")
 # The C ABI, and one translation unit of kernels per right-hand side.
 SOURCES = [os.path.join(CSRC, f) for f in (
     "gradsolve.hip", "gs_inst_harmonic.hip", "gs_inst_kepler.hip", "gs_inst_loghalo.hip",
-    "gs_inst_spinprec.hip", "gs_inst_quint.hip")]
+    "gs_inst_spinprec.hip", "gs_inst_quint.hip", "gs_inst_stiff.hip")]
 HEADERS = [os.path.join(CSRC, h) for h in (
     "gs_kernels.hpp", "gs_rhs.hpp", "gs_tableaux.hpp", "gs_ops.hpp", "gs_inst.hpp",
-    "gs_dual.hpp", "gs_de.hpp")] + [
+    "gs_dual.hpp", "gs_de.hpp", "gs_stiff.hpp")] + [
     os.path.join(ROOT, "include", "gradsolve.h")]
 OBJDIR = os.path.join(HERE, "_build")
 

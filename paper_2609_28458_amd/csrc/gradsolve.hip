@@ -19,8 +19,10 @@ namespace {
 using gs::Params;
 using gs::VjpParams;
 
-constexpr int kNumRhs = 5;
-constexpr int kNumTab = 3;
+constexpr int kNumRhs = 7;      // five explicit right-hand sides, then the two stiff ones
+constexpr int kNumTab = 4;      // three explicit pairs, then Rodas4
+constexpr int kNumExplicitRhs = 5;
+constexpr int kNumExplicitTab = 3;
 constexpr int64_t kAdjMaxLanes = 131072;  // adjoint lanes on one GPU (2 waves per SIMD)
 constexpr size_t kCounterBytes = 256;
 // Losses per adjoint launch.  Each further loss is another launch; one loss
@@ -40,19 +42,23 @@ __global__ void reset_queues_kernel(unsigned long long* c, long long n_wide) {
 }
 
 int rhs_dim(int r) {
-  static const int d[kNumRhs] = {gs::Harmonic::D, gs::Kepler::D, gs::LogHalo::D,
-                                 gs::SpinPrec::D, gs::Quint::D};
-  return d[r];
+  static const int d[kNumExplicitRhs] = {gs::Harmonic::D, gs::Kepler::D, gs::LogHalo::D,
+                                         gs::SpinPrec::D, gs::Quint::D};
+  return r < kNumExplicitRhs ? d[r] : gs_host::stiff_dim(r);
 }
 int rhs_np(int r) {
-  static const int p[kNumRhs] = {gs::Harmonic::P, gs::Kepler::P, gs::LogHalo::P,
-                                 gs::SpinPrec::P, gs::Quint::P};
-  return p[r];
+  static const int p[kNumExplicitRhs] = {gs::Harmonic::P, gs::Kepler::P, gs::LogHalo::P,
+                                         gs::SpinPrec::P, gs::Quint::P};
+  return r < kNumExplicitRhs ? p[r] : gs_host::stiff_np(r);
 }
 
+// The stiff path: Rodas4 on a stiff right-hand side (check_args requires both
+// or neither).
+bool is_stiff(const gs_solve_args* a) { return a->tableau == GS_RODAS4; }
+
 int tab_stages(int tab) {
-  static const int s[kNumTab] = {gs::Dopri5::S, gs::Tsit5::S, gs::Verner7::S};
-  return (tab >= 0 && tab < kNumTab) ? s[tab] : gs::Verner7::S;
+  static const int s[kNumExplicitTab] = {gs::Dopri5::S, gs::Tsit5::S, gs::Verner7::S};
+  return (tab >= 0 && tab < kNumExplicitTab) ? s[tab] : gs::Verner7::S;
 }
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
@@ -117,6 +123,9 @@ gs_status check_args(const gs_solve_args* a) {
   if (!(c.safety > 0.0) || !(c.alpha_min > 0.0) || !(c.alpha_max >= 1.0) ||
       !(c.alpha_min <= 1.0))
     return GS_ERR_INVALID;
+  if ((a->rhs >= kNumExplicitRhs) != is_stiff(a)) return GS_ERR_UNSUPPORTED;
+  if (is_stiff(a) && (a->ckpt_every > 0 || a->wide > 0 || c.beta1 > 0.0 || c.beta2 != 0.0))
+    return GS_ERR_UNSUPPORTED;
   if (!a->workspace) return GS_ERR_WORKSPACE;
   if (a->workspace_bytes < layout_of(a).total) return GS_ERR_WORKSPACE;
   if (((uintptr_t)a->workspace & 255) != 0) return GS_ERR_WORKSPACE;
@@ -221,8 +230,9 @@ void solve_shape(const gs_solve_args* a, int* grid, int* block) {
     *grid = (int)std::min<int64_t>(a->grid, need);
   } else {
     int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, ops(a->rhs, a->tableau).solve_fn,
-                                                     b, 0) != hipSuccess ||
+    const void* fn =
+        is_stiff(a) ? gs_host::stiff_solve_fn(a->rhs) : ops(a->rhs, a->tableau).solve_fn;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, b, 0) != hipSuccess ||
         per_cu < 1)
       per_cu = 1;
     *grid = (int)std::min<int64_t>((int64_t)per_cu * num_cus(), need);
@@ -237,6 +247,10 @@ gs_status launch_solve_all(const gs_solve_args* a) {
   hipLaunchKernelGGL(reset_queues_kernel, dim3(1), dim3(64), 0, s, P.counters, (long long)P.n_wide);
   int grid = 0, block = 0;
   solve_shape(a, &grid, &block);
+  if (is_stiff(a)) {
+    gs_host::launch_stiff(a->rhs, P, grid, block, s);
+    return hipGetLastError() == hipSuccess ? GS_OK : GS_ERR_HIP;
+  }
   if (P.n_wide > 0) {
     // One workgroup holds block / 16 groups; all wide trajectories start at
     // once, ahead of the single-lane workgroups.
@@ -285,6 +299,7 @@ gs_status gs_solve(const gs_solve_args* a) {
 gs_status gs_solve_vjp(const gs_solve_args* fwd, const gs_vjp_args* v) {
   gs_status st = check_args(fwd);
   if (st != GS_OK) return st;
+  if (is_stiff(fwd)) return GS_ERR_UNSUPPORTED;
   if (!v || v->R < 1 || v->R > 8 || !v->y0bar || !v->thetabar) return GS_ERR_INVALID;
   if (v->ybar_out && fwd->K == 0) return GS_ERR_INVALID;
   if (fwd->ckpt_every <= 0) return GS_ERR_NO_TAPE;
@@ -419,7 +434,8 @@ gs_status gs_solve_sens(const gs_solve_args* a, const gs_sens_args* sa) {
   if (st != GS_OK) return st;
   if (!sa || sa->M < 1 || sa->M > kSensMaxCols || !sa->cols || !sa->S_final) return GS_ERR_INVALID;
   if (a->K > 0 && !sa->S_out) return GS_ERR_INVALID;
-  if (a->ckpt_every > 0 || a->wide > 0 || a->schedule != GS_SCHED_QUEUE) return GS_ERR_UNSUPPORTED;
+  if (is_stiff(a) || a->ckpt_every > 0 || a->wide > 0 || a->schedule != GS_SCHED_QUEUE)
+    return GS_ERR_UNSUPPORTED;
   for (int m = 0; m < sa->M; ++m)
     if (sa->cols[m] < 0 || sa->cols[m] >= a->d + a->p) return GS_ERR_INVALID;
   if (a->n == 0) return GS_OK;
@@ -436,7 +452,7 @@ gs_status gs_de_profile(const gs_de_profile_args* A) {
   if (!A || A->n < 0 || A->K < 1 || A->iters < 0 || A->newton < 0 || A->K_data < 0)
     return GS_ERR_INVALID;
   if (A->K_data > 0 && (A->K < 4 || !A->N_data)) return GS_ERR_INVALID;
-  if (A->tableau < 0 || A->tableau >= kNumTab || !(A->rtol > 0.0) || !(A->atol >= 0.0) ||
+  if (A->tableau < 0 || A->tableau >= kNumExplicitTab || !(A->rtol > 0.0) || !(A->atol >= 0.0) ||
       !(A->N_start < 0.0) || !(A->mu >= 0.0) || !(A->trust_om > 0.0) || !(A->trust_h > 0.0))
     return GS_ERR_INVALID;
   if (A->n == 0) return GS_OK;
@@ -547,6 +563,7 @@ gs_status gs_dense_eval(const gs_solve_args* fwd, int32_t Q, const double* t_que
                         double* y_query, void* stream) {
   const gs_status st = check_args(fwd);
   if (st != GS_OK) return st;
+  if (is_stiff(fwd)) return GS_ERR_UNSUPPORTED;
   if (Q < 0 || (Q > 0 && (!t_query || !y_query))) return GS_ERR_INVALID;
   if (Q == 0 || fwd->n == 0) return GS_OK;
   const int block = 256;
@@ -568,6 +585,12 @@ gs_status gs_rhs_eval(int32_t rhs, int64_t m, const double* t, const double* y,
   const int block = 256;
   const int grid = (int)((m + block - 1) / block);
   hipStream_t s = static_cast<hipStream_t>(stream);
+  if (rhs >= kNumExplicitRhs) {
+    if (want_vjp) return GS_ERR_UNSUPPORTED;
+    if (!f) return GS_ERR_INVALID;
+    gs_host::launch_stiff_rhs(rhs, m, y, theta, f, s);
+    return hipGetLastError() == hipSuccess ? GS_OK : GS_ERR_HIP;
+  }
   switch (rhs) {
     case GS_RHS_HARMONIC:
       hipLaunchKernelGGL(gs::rhs_kernel<gs::Harmonic>, dim3(grid), dim3(block), 0, s, m, t, y,

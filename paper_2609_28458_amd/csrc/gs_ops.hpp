@@ -30,4 +30,14 @@ void ops_row_loghalo(Ops* row);
 void ops_row_spinprec(Ops* row);
 void ops_row_quint(Ops* row);
 
+// Stiff path (gs_inst_stiff.hip): the Rodas4 kernel of a stiff right-hand
+// side (GS_RHS_KIN3 / GS_RHS_KIN8), its function for the occupancy query,
+// and the right-hand side evaluation.
+const void* stiff_solve_fn(int rhs);
+void launch_stiff(int rhs, const gs::Params& P, int grid, int block, hipStream_t s);
+void launch_stiff_rhs(int rhs, int64_t m, const double* y, const double* theta, double* f,
+                      hipStream_t s);
+int stiff_dim(int rhs);
+int stiff_np(int rhs);
+
 }  // namespace gs_host

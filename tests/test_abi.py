@@ -57,7 +57,7 @@ def _args(**kw):
 
 
 @pytest.mark.parametrize("kw", [
-    dict(rhs=7), dict(tableau=3), dict(d=5), dict(p=4), dict(n=-1),
+    dict(rhs=7), dict(tableau=4), dict(d=5), dict(p=4), dict(n=-1),
     dict(y0=None), dict(theta_stride=5), dict(t_stride=2), dict(K=3),
     dict(ckpt_every=-1), dict(ckpt_every=4, ckpt_capacity=0), dict(block=100), dict(wide=-1),
     dict(block=1024), dict(refill=65), dict(schedule=5),
@@ -150,3 +150,37 @@ def test_de_profile_workspace_and_argument_checks():
         assert L.gs_de_profile(C.byref(_de_args(workspace_bytes=spline, **bad))) == 1, bad
     # n = 0 is a no-op, whatever the pointers
     assert L.gs_de_profile(C.byref(_de_args(n=0, workspace=None))) == 0
+
+
+def _stiff(**kw):
+    a = _args(rhs=5, tableau=3, d=3, p=3)
+    for k, v in kw.items():
+        setattr(a, k, v)
+    return a
+
+
+def test_stiff_path_argument_checks():
+    L = api.lib()
+    # explicit pair on a stiff right-hand side, Rodas4 on an explicit one
+    assert L.gs_solve(C.byref(_args(rhs=5, tableau=0, d=3, p=3))) == 2
+    assert L.gs_solve(C.byref(_args(tableau=3))) == 2
+    assert L.gs_solve(C.byref(_stiff(d=8))) == 1
+    assert L.gs_solve(C.byref(_stiff(rhs=6, d=8, p=11))) == 1
+    # no tape, no wide groups, I control only
+    assert L.gs_solve(C.byref(_stiff(ckpt_every=1, ckpt_capacity=10))) == 2
+    assert L.gs_solve(C.byref(_stiff(wide=4))) == 2
+    b = _stiff()
+    b.ctrl.beta2 = 0.04
+    assert L.gs_solve(C.byref(b)) == 2
+    # workspace: the queue counters only
+    assert L.gs_workspace_bytes(C.byref(_stiff(rhs=6, d=8, p=12))) == 256
+    # entry points the stiff path does not have
+    v = api.gs_vjp_args(1, None, 0x1000, 0x1000, 0x1000, 0, 0, None)
+    assert L.gs_solve_vjp(C.byref(_stiff()), C.byref(v)) == 2
+    cols = (C.c_int32 * 1)(0)
+    s = api.gs_sens_args(1, C.cast(cols, C.c_void_p), 0x1000, 0)
+    assert L.gs_solve_sens(C.byref(_stiff()), C.byref(s)) == 2
+    assert L.gs_dense_eval(C.byref(_stiff()), 1, 0x1000, 0x1000, None) == 2
+    assert L.gs_rhs_eval(5, 10, 0x1000, 0x1000, 0x1000, 0x1000, 0x1000, 0x1000, 0x1000,
+                         None) == 2
+    assert L.gs_rhs_eval(7, 10, 0x1000, 0x1000, 0x1000, 0x1000, None, None, None, None) == 1
