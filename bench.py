@@ -119,6 +119,57 @@ def cpu_baseline(w, target_thread_seconds=15.0):
                       f"{threads} threads"}
 
 
+def rodas4_flops_per_attempt(D, jac_flops, rhs_flops):
+    """Algorithmic FP64 flops of one Rodas4 attempt of the stiff kernel (fma =
+    2, division or reciprocal = 1): Jacobian; the matrix 1/(h gamma) I - J
+    (D + 2); LU with partial pivoting, sum over columns of m multipliers and
+    m^2 updates, m = D-1..0, plus D pivot reciprocals; six triangular solves
+    of 2 D^2 - D each; stage sums 70 D + 1; six right-hand sides (five stages
+    and f at the new point); y+ and the error norm 17 D + 1."""
+    lu = sum(m + 2 * m * m for m in range(D)) + D
+    return (jac_flops + D + 2 + lu + 6 * (2 * D * D - D) + 70 * D + 1 + 6 * rhs_flops
+            + 17 * D + 1)
+
+
+def stiff_bench(args, torch, api, inputs):
+    """Rodas4 kernel on the two stiff kinetics workloads (10^5 trajectories,
+    16 output times each), graph-launched, with the oracle on a seeded sample
+    of the host's cores for scale."""
+    import oracle
+
+    res = {}
+    threads = min(os.cpu_count() or 1, 16)
+    for gen, jac_f, rhs_f in ((inputs.kinetics3, 3, 7), (inputs.kinetics8, 6, 28)):
+        w = gen()
+        prob = api.make_problem(w["rhs"], w["tableau"], w["y0"], w["theta"], w["t0"], w["t1"],
+                                w["rtol"], w["atol"], w["t_out"])
+        sol = api.Solution(prob, api.Launch())
+        graph = api.Graph(sol)
+        ms = timed(lambda: graph.launch(), max(5, args.steps // 2), 2, torch)
+        torch.cuda.synchronize()
+        n = prob.n
+        attempts = int((sol.n_accepted.to(torch.int64) + sol.n_rejected).sum())
+        ok = bool((sol.status == 0).all())
+        fpa = rodas4_flops_per_attempt(prob.d, jac_f, rhs_f)
+        tf = fpa * attempts / (ms * 1e-3) / 1e12
+        idx = np.sort(np.random.default_rng(77).choice(n, 5000, replace=False))
+        t0 = time.perf_counter()
+        oracle.solve(w["rhs"], "rodas4", w["y0"][:, idx], w["theta"][:, idx], 0.0, w["t1"][idx],
+                     w["rtol"], w["atol"], w["t_out"][:, idx], nthreads=threads)
+        cpu = 5000 / (time.perf_counter() - t0)
+        res[w["rhs"]] = {
+            "workload": f"{n} stiff {w['rhs']} trajectories, Rodas4 rtol {w['rtol']:g} atol "
+                        f"{w['atol']:g}, 16 outputs", "ms": round(ms, 4),
+            "solves_per_s": n / (ms * 1e-3), "attempts": attempts, "all_ok": ok,
+            "roofline": {"bound": "alu", "flops_per_attempt": fpa, "achieved": round(tf, 3),
+                         "peak": 78.6, "unit": "TFLOP/s", "frac": round(tf / 78.6, 4)},
+            "cpu_oracle_solves_per_s": round(cpu, 1), "cpu_threads": threads}
+        log(f"[bench] stiff {w['rhs']}: {ms:.3f} ms, {n / ms * 1e3:.3e} solves/s, "
+            f"{tf:.2f} TFLOP/s ({tf / 78.6:.1%} of FP64 peak); oracle {cpu:.0f} solves/s")
+        graph.close()
+    return res
+
+
 def committed_traffic():
     """HBM bytes per launch from the committed PMC summary, if it was taken
     on the current kernel source; else None."""
@@ -383,6 +434,10 @@ def main():
             log(f"[bench] dark-energy profile ({name}): {ms_p:.3f} ms, "
                 f"{us_it:.4f} us per iteration per fit")
         out["de_profile"] = prof
+
+    # ---- stiff path: Rodas4 on 10^5 trajectories of each kinetics network --------------------
+    if not args.no_grad:
+        out["stiff"] = stiff_bench(args, torch, api, inputs)
 
     if not args.no_cpu:
         cb = cpu_baseline(w)
