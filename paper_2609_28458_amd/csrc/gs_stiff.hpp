@@ -16,6 +16,8 @@
 // Everything a lane needs lives in VGPRs: the matrix, the stages and the
 // pivot indices are indexed only by compile-time constants (row swaps are
 // per-lane branches over the candidate rows), so nothing goes to scratch.
+// Reciprocals (of the pivots, h and h gamma, and the error scales) use the
+// hardware reciprocal refined by Newton steps instead of IEEE division.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -67,6 +69,7 @@ struct Rodas4 {
 //   a -> b (k1 a),  b + c -> 2c (k2 b c),  c -> a (k3 c)
 struct Kin3 {
   static constexpr int D = 3, P = 3;
+  static constexpr int WAVES_PER_EU = 3;  // register budget of the stiff kernel
   template <class T>
   struct ParT {
     T k1, k2, k3;
@@ -103,6 +106,7 @@ struct Kin3 {
 //   source -> y5 (s), y5 -> sink (k12)
 struct Kin8 {
   static constexpr int D = 8, P = 12;
+  static constexpr int WAVES_PER_EU = 1;
   template <class T>
   struct ParT {
     T k[P];
@@ -180,19 +184,22 @@ __device__ __forceinline__ bool lu_factor(double (&M)[D][D], int (&piv)[D], doub
       best = a > best ? a : best;
     });
     piv[k] = p;
-    sfor<D - k - 1>([&](auto R) {
-      constexpr int r = k + 1 + decltype(R)::value;
-      if (p == r) {
+    // The swap runs under a per-lane branch: a wavefront in which no lane
+    // pivots at this column skips it.
+    if (p != k) {
+      sfor<D - k - 1>([&](auto R) {
+        constexpr int r = k + 1 + decltype(R)::value;
+        const bool sw = p == r;
 #pragma unroll
         for (int c = 0; c < D; ++c) {
-          const double x = M[k][c];
-          M[k][c] = M[r][c];
-          M[r][c] = x;
+          const double a = M[k][c], b = M[r][c];
+          M[k][c] = sw ? b : a;
+          M[r][c] = sw ? a : b;
         }
-      }
-    });
+      });
+    }
     ok = ok && best > 0.0 && (best - best) == 0.0;  // false for NaN and infinity
-    inv[k] = 1.0 / M[k][k];
+    inv[k] = fast_rcp(M[k][k]);
     sfor<D - k - 1>([&](auto R) {
       constexpr int r = k + 1 + decltype(R)::value;
       const double l = M[r][k] * inv[k];
@@ -204,29 +211,34 @@ __device__ __forceinline__ bool lu_factor(double (&M)[D][D], int (&piv)[D], doub
   return ok;
 }
 
-// x <- M^{-1} x with the factors of lu_factor.
+// x <- M^{-1} x with the factors of lu_factor; `swapped` says whether any
+// row was exchanged (the permutation is skipped, per lane, when none was).
+// Substitution runs column by column, so the updates of one step are
+// independent of each other.
 template <int D>
 __device__ __forceinline__ void lu_solve(const double (&M)[D][D], const int (&piv)[D],
-                                         const double (&inv)[D], double (&x)[D]) {
-  sfor<D>([&](auto K) {
-    constexpr int k = decltype(K)::value;
-    sfor<D - k - 1>([&](auto R) {
-      constexpr int r = k + 1 + decltype(R)::value;
-      const bool sw = piv[k] == r;
-      const double a = x[k], b = x[r];
-      x[k] = sw ? b : a;
-      x[r] = sw ? a : b;
+                                         const double (&inv)[D], bool swapped, double (&x)[D]) {
+  if (swapped) {
+    sfor<D>([&](auto K) {
+      constexpr int k = decltype(K)::value;
+      sfor<D - k - 1>([&](auto R) {
+        constexpr int r = k + 1 + decltype(R)::value;
+        const bool sw = piv[k] == r;
+        const double a = x[k], b = x[r];
+        x[k] = sw ? b : a;
+        x[r] = sw ? a : b;
+      });
     });
-  });
+  }
 #pragma unroll
-  for (int r = 1; r < D; ++r)
+  for (int c = 0; c < D - 1; ++c)
 #pragma unroll
-    for (int c = 0; c < r; ++c) x[r] = fma(-M[r][c], x[c], x[r]);
+    for (int r = c + 1; r < D; ++r) x[r] = fma(-M[r][c], x[c], x[r]);
 #pragma unroll
-  for (int r = D - 1; r >= 0; --r) {
+  for (int c = D - 1; c >= 0; --c) {
+    x[c] *= inv[c];
 #pragma unroll
-    for (int c = r + 1; c < D; ++c) x[r] = fma(-M[r][c], x[c], x[r]);
-    x[r] *= inv[r];
+    for (int r = 0; r < c; ++r) x[r] = fma(-M[r][c], x[c], x[r]);
   }
 }
 
@@ -241,7 +253,7 @@ __device__ __forceinline__ double rodas_attempt(const Inputs<F>& in, double t, d
   constexpr int D = F::D, S = TB::S;
   double M[D][D];
   F::jac(y, in.par, M);
-  const double ig = 1.0 / (h * TB::GAMMA);
+  const double ig = fast_rcp(h * TB::GAMMA);
 #pragma unroll
   for (int r = 0; r < D; ++r)
 #pragma unroll
@@ -249,7 +261,10 @@ __device__ __forceinline__ double rodas_attempt(const Inputs<F>& in, double t, d
   int piv[D];
   double inv[D];
   const bool ok = lu_factor<D>(M, piv, inv);
-  const double ih = 1.0 / h;
+  bool swapped = false;
+#pragma unroll
+  for (int k = 0; k < D; ++k) swapped = swapped || piv[k] != k;
+  const double ih = fast_rcp(h);
   double u[S][D];
   sfor<S>([&](auto I) {
     constexpr int i = decltype(I)::value;
@@ -275,7 +290,7 @@ __device__ __forceinline__ double rodas_attempt(const Inputs<F>& in, double t, d
 #pragma unroll
       for (int c = 0; c < D; ++c) x[c] = fma(ih, x[c], fy[c]);
     }
-    lu_solve<D>(M, piv, inv, x);
+    lu_solve<D>(M, piv, inv, swapped, x);
 #pragma unroll
     for (int c = 0; c < D; ++c) u[i][c] = x[c];
   });
@@ -289,135 +304,155 @@ __device__ __forceinline__ double rodas_attempt(const Inputs<F>& in, double t, d
     });
     yn[c] = acc;
     const double sc = fma(in.rtol, dmax(fabs(y[c]), fabs(acc)), in.atol);
-    const double r = u[S - 1][c] / sc;
+    const double r = u[S - 1][c] * fast_rcp1(sc);
     sq = fma(r, r, sq);
   }
   const double en2 = sq * (1.0 / D);
   return ok ? en2 : __builtin_nan("");
 }
 
-// Persistent stiff solve: each lane takes trajectories from the queue (or
-// exactly one, in static mode) and integrates them with rodas_attempt.
-// Lanes refill on their own: a lane that finishes takes the next queue
-// position at once (an atomic per finished trajectory).
+// Persistent stiff solve, organised like the explicit forward kernel: an
+// outer loop retires and refills lanes, an inner loop runs attempts of the
+// live lanes until one of them finishes.  A wavefront refills once at least
+// `refill` lanes are idle, with one atomic for all of them (a ballot and a
+// prefix count in wave-uniform code), so the loads and the starting step of
+// new trajectories are shared by many lanes instead of stalling the wave
+// once per lane.  Static mode gives each lane one trajectory.
 template <class F>
-__global__ void __launch_bounds__(256) stiff_kernel(Params P) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(F::WAVES_PER_EU)))
+stiff_kernel(Params P) {
   using TB = Rodas4;
   constexpr int D = F::D;
   const int64_t n = P.n;
-  const int64_t lane = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  bool first = true;
-  int64_t i = 0;
+  const int lane = threadIdx.x & 63;
+  int64_t idx = 0;
+  bool live = false;
+  bool queue_empty = P.sched_static != 0;  // wave-uniform
   Inputs<F> in;
   double y[D], f0[D];
   double t = 0.0, h = 0.0;
-  int32_t nacc = 0, nrej = 0, nanrun = 0, kk = 0, status = ST_OK;
+  int32_t nacc = 0, nrej = 0, nanrun = 0, kk = 0;
 
   auto store_node = [&](int q, const double (&v)[D]) {
 #pragma unroll
-    for (int c = 0; c < D; ++c) P.y_out[((int64_t)c * P.K + q) * n + i] = v[c];
+    for (int c = 0; c < D; ++c) P.y_out[((int64_t)c * P.K + q) * n + idx] = v[c];
   };
-  auto finish = [&]() {
+  auto finish = [&](int32_t st) {
     for (int q = kk; q < P.K; ++q) {
 #pragma unroll
-      for (int c = 0; c < D; ++c) P.y_out[((int64_t)c * P.K + q) * n + i] = __builtin_nan("");
+      for (int c = 0; c < D; ++c) P.y_out[((int64_t)c * P.K + q) * n + idx] = __builtin_nan("");
     }
 #pragma unroll
-    for (int c = 0; c < D; ++c) P.y_final[(int64_t)c * n + i] = y[c];
-    P.n_acc[i] = nacc;
-    P.n_rej[i] = nrej;
-    P.status[i] = status;
+    for (int c = 0; c < D; ++c) P.y_final[(int64_t)c * n + idx] = y[c];
+    P.n_acc[idx] = nacc;
+    P.n_rej[idx] = nrej;
+    P.status[idx] = st;
+    live = false;
   };
-  // Takes trajectories until one needs integrating; false when none is left.
-  auto start = [&]() -> bool {
-    for (;;) {
-      int64_t pos;
-      if (P.sched_static) {
-        pos = first ? lane : n;
-      } else {
-        pos = (int64_t)atomicAdd(&P.counters[0], 1ull);
-      }
-      first = false;
-      if (pos >= n) return false;
-      i = P.order ? P.order[pos] : pos;
-      load_inputs<F>(P, i, in, y);
-      nacc = nrej = nanrun = kk = 0;
-      status = ST_OK;
-      t = in.t0;
-      bool fin = true;
+  // Take trajectory i: load, validate, nodes at t0, first evaluation,
+  // starting step.  Trajectories with nothing to integrate finish here.
+  auto start = [&](int64_t i) {
+    idx = i;
+    live = true;
+    nacc = nrej = nanrun = kk = 0;
+    load_inputs<F>(P, i, in, y);
+    t = in.t0;
+    bool fin = true;
 #pragma unroll
-      for (int c = 0; c < D; ++c) fin = fin && (y[c] - y[c]) == 0.0;
-      if (!inputs_valid<F>(P, i, in)) {
-        status = ST_BAD_INPUT;
-        finish();
-        continue;
-      }
-      while (kk < P.K && node_time(P, kk, i) <= in.t0) store_node(kk++, y);
-      if (!fin) status = ST_NONFINITE;
-      if (!fin || !(in.t1 > in.t0)) {
-        finish();
-        continue;
-      }
-      F::f(t, y, in.par, f0);
-      h = P.h0 > 0.0 ? dmin(P.h0, in.t1 - in.t0) : initial_step<TB, F>(in, y, f0);
-      return true;
+    for (int c = 0; c < D; ++c) fin = fin && (y[c] - y[c]) == 0.0;
+    if (!inputs_valid<F>(P, i, in)) {
+      finish(ST_BAD_INPUT);
+      return;
     }
+    while (kk < P.K && node_time(P, kk, i) <= in.t0) store_node(kk++, y);
+    if (!fin) {
+      finish(ST_NONFINITE);
+      return;
+    }
+    if (!(in.t1 > in.t0)) {
+      finish(ST_OK);
+      return;
+    }
+    F::f(t, y, in.par, f0);
+    h = P.h0 > 0.0 ? dmin(P.h0, in.t1 - in.t0) : initial_step<TB, F>(in, y, f0);
   };
 
-  bool live = start();
-  while (live) {
-    bool done = false;
-    if ((int64_t)nacc + nrej >= P.max_steps) {
-      status = ST_MAX_STEPS;
-      done = true;
-    } else {
-      const double stop = kk < P.K ? node_time(P, kk, i) : in.t1;
-      double hh = h;
-      bool land = false;
-      if (t + hh >= stop) {
-        hh = stop - t;
-        land = true;
-      }
-      double yn[D];
-      const double en2 = rodas_attempt<F>(in, t, hh, y, f0, yn);
-      const bool finite = (en2 - en2) == 0.0;
-      const double factor = step_factor<TB>(P, en2, 1.0, finite);
-      if (finite && en2 <= 1.0) {
-        ++nacc;
-        t = land ? stop : t + hh;
-        bool yfin = true;
-#pragma unroll
-        for (int c = 0; c < D; ++c) {
-          y[c] = yn[c];
-          yfin = yfin && (yn[c] - yn[c]) == 0.0;
+  if (P.sched_static) {
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g < n) start(g);
+  }
+  for (;;) {
+    if (!queue_empty) {
+      const uint64_t idle = __ballot(!live);
+      const int nidle = __popcll(idle);
+      if (nidle >= P.refill) {
+        unsigned long long base = 0;
+        if (lane == 0) base = atomicAdd(P.counters, (unsigned long long)nidle);
+        base = first_lane(base);
+        if (base + (unsigned long long)nidle >= (unsigned long long)n) queue_empty = true;
+        if (!live) {
+          const unsigned long long pos = base + __popcll(idle & lanemask_lt());
+          if (pos < (unsigned long long)n) {
+            const int64_t id = P.order ? P.order[pos] : (int64_t)pos;
+            if (id >= 0 && id < n) start(id);  // a bad permutation entry is skipped
+          }
         }
-        if (!yfin) {
-          status = ST_NONFINITE;
-          done = true;
+      }
+    }
+    if (__ballot(live) == 0) {
+      if (queue_empty) break;
+      continue;
+    }
+    int32_t st = -1;  // status once this lane's trajectory has finished
+    for (;;) {
+      if (live) {
+        if ((int64_t)nacc + nrej >= P.max_steps) {
+          st = ST_MAX_STEPS;
         } else {
-          while (kk < P.K && node_time(P, kk, i) <= t) store_node(kk++, y);
-          F::f(t, y, in.par, f0);
-          nanrun = 0;
-          done = t >= in.t1;
-        }
-      } else {
-        ++nrej;
-        nanrun = finite ? 0 : nanrun + 1;
-        if (nanrun >= 50) {
-          status = ST_NONFINITE;
-          done = true;
+          const double stop = kk < P.K ? node_time(P, kk, idx) : in.t1;
+          double hh = h;
+          bool land = false;
+          if (t + hh >= stop) {
+            hh = stop - t;
+            land = true;
+          }
+          double yn[D];
+          const double en2 = rodas_attempt<F>(in, t, hh, y, f0, yn);
+          const bool finite = (en2 - en2) == 0.0;
+          const double factor = step_factor<TB>(P, en2, 1.0, finite);
+          bool done = false;
+          if (finite && en2 <= 1.0) {
+            ++nacc;
+            t = land ? stop : t + hh;
+            bool yfin = true;
+#pragma unroll
+            for (int c = 0; c < D; ++c) {
+              y[c] = yn[c];
+              yfin = yfin && (yn[c] - yn[c]) == 0.0;
+            }
+            if (!yfin) {
+              st = ST_NONFINITE;
+            } else {
+              while (kk < P.K && node_time(P, kk, idx) <= t) store_node(kk++, y);
+              F::f(t, y, in.par, f0);
+              nanrun = 0;
+              done = t >= in.t1;
+            }
+          } else {
+            ++nrej;
+            nanrun = finite ? 0 : nanrun + 1;
+            if (nanrun >= 50) st = ST_NONFINITE;
+          }
+          h = hh * factor;
+          if (done)
+            st = ST_OK;
+          else if (st < 0 && underflow(h, t))
+            st = ST_DT_UNDERFLOW;
         }
       }
-      h = hh * factor;
-      if (!done && underflow(h, t)) {
-        status = ST_DT_UNDERFLOW;
-        done = true;
-      }
+      if (__ballot(live && st >= 0) != 0) break;
     }
-    if (done) {
-      finish();
-      live = start();
-    }
+    if (live && st >= 0) finish(st);
   }
 }
 
