@@ -2,7 +2,8 @@
 
   python profiles/make_summary.py trace <results.db> "<command>" [name filter]
       kernel-trace statistics (top kernels and per-dispatch durations),
-      optionally only kernels whose name contains the filter
+      optionally only kernels whose name contains the filter (alternatives
+      separated by "|")
   python profiles/make_summary.py traffic <fetch.csv> <write.csv> <kernel-sha> "<commands>"
       HBM bytes per solve launch from FETCH_SIZE / WRITE_SIZE passes, each
       scaled by what the same counter reads for a 1 GiB device copy
@@ -16,6 +17,11 @@ GIB_KIB = 1 << 20  # FETCH_SIZE / WRITE_SIZE count KiB
 
 def trace(db, cmd, only=""):
     c = sqlite3.connect(db)
+    alts = [a for a in only.split("|") if a]
+
+    def keep(name):
+        return not alts or any(a in name for a in alts)
+
     print(f"command: `{cmd}`\n")
     if only:
         print(f"kernels whose name contains `{only}`\n")
@@ -24,16 +30,18 @@ def trace(db, cmd, only=""):
     # top_kernels reports microseconds, the kernels table nanoseconds.
     for name, calls, tot, avg, pct in c.execute(
             "select name, total_calls, total_duration, average, percentage from top_kernels"):
-        if only and only not in name:
+        if not keep(name):
             continue
         print(f"| {name[:90]} | {calls} | {tot / 1e3:.3f} | {avg / 1e3:.4f} | {pct:.2f} |")
     rows = list(c.execute("select name, duration, grid_x, workgroup_x, vgpr_count, "
                           "accum_vgpr_count, scratch_size from kernels order by start"))
-    solve = [r for r in rows if ("solve_kernel" in r[0] or "vjp_kernel" in r[0])
-             and (not only or only in r[0])]
+    solve = [r for r in rows if any(k in r[0] for k in ("solve_kernel", "vjp_kernel",
+                                                        "stiff_kernel", "sens_kernel"))
+             and keep(r[0])]
     if solve:
-        print("\nper dispatch (solve/vjp kernels): duration ms, grid, block, vgpr, agpr, scratch")
-        for r in solve:
+        print("\nper dispatch (solver kernels, at most 12): duration ms, grid, block, vgpr, agpr, "
+              "scratch")
+        for r in solve[:12]:
             print(f"- {r[0][:70]}: {r[1] / 1e6:.3f} ms, grid {r[2]}, block {r[3]}, "
                   f"vgpr {r[4]}, agpr {r[5]}, scratch {r[6]}")
 
