@@ -386,7 +386,7 @@ void sens_launches(const gs_solve_args* a, const gs_sens_args* sa) {
 // S_out [3][2][K][n], S_final [3][2][n], and three int32 [n] arrays.
 struct DeLayout {
   size_t counters, scal, theta, y0, y_out, y_final, S_out, S_final, nacc, nrej, st;
-  size_t W, tmp, node, total;  // spline only: weights, their scratch, node values
+  size_t W, tmp, total;  // spline only: weights and their scratch
 };
 DeLayout de_layout(const gs_de_profile_args* A) {
   DeLayout L;
@@ -411,7 +411,6 @@ DeLayout de_layout(const gs_de_profile_args* A) {
   const size_t Kd = A->K_data > 0 ? (size_t)A->K_data : 0;
   L.W = take(Kd * K * 8);
   L.tmp = take(Kd ? 3 * K * K * 8 : 0);
-  L.node = take(Kd ? 4 * K * n * 8 : 0);
   L.total = off;
   return L;
 }
@@ -524,12 +523,10 @@ gs_status gs_de_profile(const gs_de_profile_args* A) {
   g.sigma = A->sigma;
   g.Kd = A->K_data > 0 ? A->K_data : A->K;
   g.W = nullptr;
-  g.node = nullptr;
   if (A->K_data > 0) {
     hipLaunchKernelGGL(gs::de::spline_weights_kernel, dim3((A->K + 63) / 64), dim3(64), 0, s,
                        A->K, A->N_nodes, A->K_data, A->N_data, D(L.tmp), D(L.W));
     g.W = D(L.W);
-    g.node = D(L.node);
   }
   g.status = I(L.st);
   g.mu = A->mu;

@@ -144,7 +144,6 @@ struct GnArgs {
   const double* sigma;    // [2][Kd]
   int32_t Kd;             // data points (= K without spline)
   const double* W;        // [Kd][K] spline weights, or null: data at the nodes
-  double* node;           // [4][K][n] node values (D_M, D_H, dD_M/dOm, dD_H/dOm) with W
   const int32_t* status;  // [n] of the solve
   double mu, trust_om, trust_h;
   int32_t update;
@@ -157,7 +156,7 @@ struct GnArgs {
   int32_t* status_out;    // [n] worst solver status
 };
 
-__global__ void gn_kernel(GnArgs A) {
+__global__ void __launch_bounds__(256) gn_kernel(GnArgs A) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t n = A.n;
   if (i >= n) return;
@@ -209,35 +208,48 @@ __global__ void gn_kernel(GnArgs A) {
   };
   // D_M at every data point, then D_H (the order of the residual vector)
   if (!A.W) {
+#pragma unroll 4
     for (int k = 0; k < A.K; ++k) {
       double d;
       const double D = node_dm(k, d);
       add(D, d, 0, k);
     }
+#pragma unroll 4
     for (int k = 0; k < A.K; ++k) {
       double d;
       const double D = node_dh(k, d);
       add(D, d, 1, k);
     }
   } else {
-    const int64_t KN = (int64_t)A.K * n;
-    for (int k = 0; k < A.K; ++k) {
-      double d0, d1;
-      A.node[k * n + i] = node_dm(k, d0);
-      A.node[KN + k * n + i] = node_dh(k, d1);
-      A.node[2 * KN + k * n + i] = d0;
-      A.node[3 * KN + k * n + i] = d1;
-    }
-    for (int q = 0; q < 2; ++q) {
-      for (int j = 0; j < A.Kd; ++j) {
-        const double* w = A.W + (int64_t)j * A.K;
-        double D = 0.0, d = 0.0;
-        for (int k = 0; k < A.K; ++k) {
-          D = fma(w[k], A.node[q * KN + k * n + i], D);
-          d = fma(w[k], A.node[(2 + q) * KN + k * n + i], d);
+    // One pass over the nodes per chunk of data points, the spline sums of
+    // the chunk in registers (the weights are the same for every fit).
+    constexpr int kChunk = 8;
+    for (int j0 = 0; j0 < A.Kd; j0 += kChunk) {
+      double sD[2][kChunk], sd[2][kChunk];
+#pragma unroll
+      for (int jj = 0; jj < kChunk; ++jj) sD[0][jj] = sD[1][jj] = sd[0][jj] = sd[1][jj] = 0.0;
+      // unrolled so the loads of several nodes are in flight together
+#pragma unroll 8
+      for (int k = 0; k < A.K; ++k) {
+        double d0, d1;
+        const double DM = node_dm(k, d0);
+        const double DH = node_dh(k, d1);
+#pragma unroll
+        for (int jj = 0; jj < kChunk; ++jj) {
+          if (j0 + jj < A.Kd) {
+            const double w = A.W[(int64_t)(j0 + jj) * A.K + k];
+            sD[0][jj] = fma(w, DM, sD[0][jj]);
+            sd[0][jj] = fma(w, d0, sd[0][jj]);
+            sD[1][jj] = fma(w, DH, sD[1][jj]);
+            sd[1][jj] = fma(w, d1, sd[1][jj]);
+          }
         }
-        add(D, d, q, j);
       }
+#pragma unroll
+      for (int q = 0; q < 2; ++q)
+#pragma unroll
+        for (int jj = 0; jj < kChunk; ++jj)
+          if (j0 + jj < A.Kd) add(sD[q][jj], sd[q][jj], q, j0 + jj);
     }
   }
   A.chi2[i] = chi2;

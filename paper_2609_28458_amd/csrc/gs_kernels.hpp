@@ -454,7 +454,16 @@ __device__ __forceinline__ Attempt attempt(const Params& P, Traj<TB, F, T>& s,
       on_accept(s, a.t_start, hh, ystart);
     }
   }
-  if constexpr (TB::FSAL) {
+  if constexpr (TB::FSAL && !std::is_same<T, double>::value) {
+    // For dual numbers the first stage is copied under the accept branch:
+    // a select between the two stage arrays placed after that branch was
+    // turned into a choice between their addresses, which kept the lane's
+    // whole state in scratch memory.
+    if (acc) {
+#pragma unroll
+      for (int c = 0; c < D; ++c) s.k[0][c] = s.k[S - 1][c];
+    }
+  } else if constexpr (TB::FSAL) {
 #pragma unroll
     for (int c = 0; c < D; ++c) s.k[0][c] = ad::select(acc, s.k[S - 1][c], s.k[0][c]);
   } else {

@@ -139,7 +139,7 @@ def test_de_profile_workspace_and_argument_checks():
     n, K, Kd = 1000, 64, 7
     direct = sum(_al(b) for b in (256, 32, 4 * n * 8, 3 * n * 8, 3 * K * n * 8, 3 * n * 8,
                                   6 * K * n * 8, 6 * n * 8, 4 * n, 4 * n, 4 * n, 0, 0, 0))
-    spline = direct + _al(Kd * K * 8) + _al(3 * K * K * 8) + _al(4 * K * n * 8)
+    spline = direct + _al(Kd * K * 8) + _al(3 * K * K * 8)
     assert L.gs_de_profile_workspace_bytes(C.byref(_de_args(K_data=0))) == direct
     assert L.gs_de_profile_workspace_bytes(C.byref(_de_args())) == spline
     assert L.gs_de_profile_workspace_bytes(C.byref(_de_args(K_data=-1))) == 0
