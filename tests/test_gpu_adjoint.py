@@ -238,3 +238,29 @@ def test_dense_queries_match_oracle_nodes(orc, tab, taped):
     o = oracle_solve(orc, {**w, "t_out": tq})
     err = np.abs(yq - o["y_out"]) / np.maximum(np.abs(o["y_out"]), 1.0)
     assert err.max() < 1e-9, err.max()
+
+
+@pytest.mark.parametrize("k", [1, 5], ids=["store", "ckpt5"])
+def test_final_cotangents_with_output_nodes(orc, k):
+    """A solve with output nodes differentiated through its final state only
+    (no node cotangents): the node variant of the adjoint with zero node
+    terms."""
+    name, make = CASES[0]
+    w = make(120)
+    w["tableau"] = "tsit5"
+    prob = _problem(w)
+    assert prob.K > 0
+    d, n = prob.d, prob.n
+    p = api.NPARAM[prob.rhs]
+    ybf = np.random.default_rng(12).normal(size=(1, d, n))
+    sol = _solve_taped(prob, k=k, cap=20000 if k == 1 else None)
+    assert np.all(sol.status.cpu().numpy() == 0)
+    y0b, thb = api.solve_vjp(sol, ybar_final=ybf)
+    torch.cuda.synchronize()
+    th = w["theta"] if np.ndim(w["theta"]) == 2 else np.repeat(
+        np.asarray(w["theta"])[:, None], n, axis=1)
+    o = oracle_solve(orc, {**w, "theta": th}, sens_cols=list(range(d + p)))
+    gy, gt = _fs_grad(o, d, None, ybf[0])
+    G = np.concatenate([y0b[0].cpu().numpy(), thb[0].cpu().numpy()])
+    R = np.concatenate([gy, gt])
+    assert (np.abs(G - R) / np.maximum(np.abs(R).max(axis=0), 1.0)).max() < 1e-8
