@@ -163,7 +163,7 @@ typedef struct gs_solve_args {
   int32_t block;         /* lanes per workgroup: 64, 128, 192 or 256        */
   int32_t grid;          /* workgroups of the persistent grid               */
   int32_t refill;        /* refill a wavefront once this many lanes idle,
-                            1..64                                           */
+                            1..64 (0: 8)                                    */
   int32_t wide;          /* the first `wide` trajectories of the queue order
                             run on 16 lanes each (one state component per
                             lane) in the same launch, for the long tail of

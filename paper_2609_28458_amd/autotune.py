@@ -22,7 +22,7 @@ CACHE = os.environ.get("GS_AUTOTUNE_CACHE",
                        os.path.join(os.path.expanduser("~"), ".cache", "gradsolve_autotune.json"))
 
 BLOCKS = (64, 128, 256)
-REFILLS = (1, 16, 64)
+REFILLS = (1, 4, 8, 16, 64)
 CKPT = (1, 8, 32, 128)  # 1 = store mode: every accepted step on the tape
 
 

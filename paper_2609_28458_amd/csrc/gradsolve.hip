@@ -168,7 +168,7 @@ Params make_params(const gs_solve_args* a) {
   P.counters = reinterpret_cast<unsigned long long*>(ws);
   P.tape = a->ckpt_every > 0 ? reinterpret_cast<double*>(ws + L.tape_off) : nullptr;
   P.order = a->order;
-  P.refill = a->refill > 0 ? a->refill : 16;
+  P.refill = a->refill > 0 ? a->refill : 8;
   P.sched_static = a->schedule == GS_SCHED_STATIC ? 1 : 0;
   P.n_wide = std::min<int64_t>(a->wide, a->n);
   P.wide_blocks = 0;  // set with the launch shape
