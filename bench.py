@@ -185,6 +185,73 @@ def stiff_bench(args, torch, api, inputs):
     return res
 
 
+def paper_workloads(torch, api, inputs, autotune):
+    """Microseconds per trajectory on the paper's three ensembles at 10^6
+    trajectories, beside the figures the paper prints for one H200 NVL
+    (context only: other hardware, and inputs drawn by this library's own
+    recipes)."""
+    res = {}
+    # streams: forward, and forward with the sensitivities to (v_c, q) in the same launch
+    w = inputs.streams()
+    n = w["y0"].shape[1]
+    prob = api.make_problem(w["rhs"], w["tableau"], w["y0"], w["theta"], w["t0"], w["t1"],
+                            w["rtol"], w["atol"])
+    launch = autotune.tune_forward(prob, use_cache=False)
+    sol = api.Solution(prob, launch)
+    ms_f = timed(lambda: sol.run(), 5, 1, torch)
+    att = (sol.n_accepted + sol.n_rejected).to(torch.float64).mean().item()
+    ms_s = timed(lambda: api.solve_sens(prob, w["grad_cols"]), 3, 1, torch)
+    res["streams"] = {"workload": f"{n} stream orbits, Tsit5 3.16e-7, 3.7 periods, final state",
+                      "mean_attempts": round(att, 1),
+                      "us_per_orbit_forward": round(ms_f * 1e3 / n, 5),
+                      "us_per_orbit_with_sensitivities": round(ms_s * 1e3 / n, 5),
+                      "paper_h200_us": {"forward": 0.12, "with_sensitivities": 0.22,
+                                        "mean_attempts": 171}}
+    del sol
+    # dark-energy distances at 7 redshifts, amplitude supplied or solved for flatness
+    w = inputs.quintessence(n=1_000_000)
+    n = w["y0"].shape[1]
+    prob = api.make_problem(w["rhs"], w["tableau"], w["y0"], w["theta"], w["t0"], w["t1"],
+                            w["rtol"], w["atol"], w["t_out"])
+    sol = api.Solution(prob, autotune.tune_forward(prob, use_cache=False))
+    ms_a = timed(lambda: sol.run(), 5, 1, torch)
+    del sol
+    th = torch.as_tensor(w["theta"], device="cuda")
+    K = len(w["t_out"])
+
+    data = torch.zeros((2, K, n), dtype=torch.float64, device="cuda")
+    sig = torch.ones((2, K), dtype=torch.float64, device="cuda")
+    h1 = torch.ones_like(th[1])
+
+    def solved():
+        return api.de_profile(th[1], th[2], h1, th[0], float(w["theta"][3, 0]), w["t_out"], data,
+                              sig, iters=0, newton=3, tableau=w["tableau"], N_start=w["t0"],
+                              rtol=w["rtol"], atol=w["atol"])
+
+    ms_b = timed(solved, 3, 1, torch)
+    res["dark_energy"] = {"workload": f"{n} cosmologies, Dopri5 1.78e-4, 7 redshifts",
+                          "us_per_cosmology_a0_supplied": round(ms_a * 1e3 / n, 5),
+                          "us_per_cosmology_a0_solved": round(ms_b * 1e3 / n, 5),
+                          "a0_solved_includes": "3 Newton solves with S_a0, then the distances "
+                                                "with their derivative along flat models",
+                          "paper_h200_us": {"a0_supplied": 0.0037, "a0_solved": 0.051}}
+    # spin precession in the paper's setting, r = 100 -> 10
+    w = inputs.spin_precession(n=1_000_000)
+    n = w["y0"].shape[1]
+    prob = api.make_problem(w["rhs"], w["tableau"], w["y0"], w["theta"], 100.0 ** -0.5, w["t1"],
+                            w["rtol"], w["atol"])
+    sol = api.Solution(prob, api.Launch())
+    ms_p = timed(lambda: sol.run(), 2, 1, torch)
+    att = (sol.n_accepted + sol.n_rejected).to(torch.float64).mean().item()
+    res["spin_precession"] = {"workload": f"{n} binaries, Verner 7 3.16e-9, r = 100 -> 10",
+                              "mean_attempts": round(att, 1),
+                              "us_per_binary": round(ms_p * 1e3 / n, 4),
+                              "paper_h200_us": {"verner7": 3.2, "mean_attempts": 911}}
+    del sol
+    log(f"[bench] paper workloads: {json.dumps(res)}")
+    return res
+
+
 def committed_traffic():
     """HBM bytes per launch from the committed PMC summary, if it was taken
     on the current kernel source; else None."""
@@ -454,6 +521,10 @@ def main():
     # ---- stiff path: Rodas4 on 10^5 trajectories of each kinetics network --------------------
     if not args.no_grad:
         out["stiff"] = stiff_bench(args, torch, api, inputs)
+
+    # ---- the paper's own per-trajectory workloads at 10^6 (its H200 figures as context) -------
+    if not args.no_grad:
+        out["paper_workloads"] = paper_workloads(torch, api, inputs, autotune)
 
     if not args.no_cpu:
         cb = cpu_baseline(w)

@@ -56,6 +56,37 @@ def orbits_forward(n=1000, seed=1):
                 rtol=1e-8, atol=1e-10, t_out=50.0 * np.arange(1, 65) / 64.0)
 
 
+def streams(n=1_000_000, seed=9, periods=3.7):
+    """The paper's stream orbits (Section on streams): shared halo v_c = 1,
+    R_c = 0.2, q = 0.7, orbits from near-circular to eccentric, in and out of
+    the plane: R ~ U[0.5, 2], z ~ U[-0.3, 0.3], phi ~ U[0, 2 pi); speed =
+    f v_circ(R, z), f ~ U[0.6, 1]; direction tilted from the azimuthal unit
+    vector by alpha ~ U[0, pi/4] towards cos(beta) R_hat + sin(beta) z_hat,
+    beta ~ U[0, 2 pi).  Each orbit runs for `periods` circular periods
+    2 pi R / v_circ at its starting point; Tsit5 at rtol = atol = 3.16e-7;
+    final state only.  The speed and tilt ranges are set so that the mean
+    number of step attempts matches the paper's printed 171 (170.9 on the
+    oracle).  Derivatives are taken with respect to (v_c, q): sensitivity
+    columns 6 and 7."""
+    rng = _rng(seed)
+    v0, q, rc = 1.0, 0.7, 0.2
+    R = rng.uniform(0.5, 2.0, n)
+    z = rng.uniform(-0.3, 0.3, n)
+    ph = rng.uniform(0.0, 2.0 * np.pi, n)
+    vcirc = v0 * R / np.sqrt(R * R + z * z / (q * q) + rc * rc)
+    f = rng.uniform(0.6, 1.0, n)
+    alpha = rng.uniform(0.0, 0.25 * np.pi, n)
+    beta = rng.uniform(0.0, 2.0 * np.pi, n)
+    Rhat = np.stack([np.cos(ph), np.sin(ph), np.zeros(n)])
+    phat = np.stack([-np.sin(ph), np.cos(ph), np.zeros(n)])
+    zhat = np.stack([np.zeros(n), np.zeros(n), np.ones(n)])
+    dirv = np.cos(alpha) * phat + np.sin(alpha) * (np.cos(beta) * Rhat + np.sin(beta) * zhat)
+    y0 = np.concatenate([np.stack([R * np.cos(ph), R * np.sin(ph), z]), f * vcirc * dirv])
+    t1 = periods * 2.0 * np.pi * R / vcirc
+    return dict(rhs="loghalo", tableau="tsit5", y0=y0, theta=np.array([v0, q, rc]), t0=0.0,
+                t1=t1, rtol=3.16e-7, atol=3.16e-7, t_out=None, grad_cols=[6, 7])
+
+
 def orbits_uneven(n=100_000, seed=2):
     """Uneven batch: per-orbit v0 ~ U[0.9, 1.1], q ~ U[0.7, 1], rc ~ U[0.05, 0.3],
     t_end ~ logU[10, 500], rtol ~ logU[1e-9, 1e-6] (atol = rtol), Tsit5,
