@@ -60,6 +60,45 @@ def test_orbits_forward_budget(orc):
     assert np.all(np.isfinite(eps)) and _p99(eps) <= 1e-4, _p99(eps)
 
 
+def _orbit_scales(y, v0, q, rc):
+    """r_E and v_E of each orbit (eq:st-scales) from its energy."""
+    Dn = rc * rc + y[0] ** 2 + y[1] ** 2 + y[2] ** 2 / q ** 2
+    E = 0.5 * (y[3] ** 2 + y[4] ** 2 + y[5] ** 2) + 0.5 * v0 * v0 * np.log(Dn)
+    return np.sqrt(np.exp(2 * E / v0 ** 2) - rc * rc), np.sqrt(2 * E - v0 * v0 * np.log(rc * rc))
+
+
+def test_streams_within_the_paper_budgets(orc):
+    """The paper's stream workload (10^4 orbits of inputs.streams, Tsit5 at
+    3.16e-7): the final state and its sensitivity to (v_c, q), taken in the
+    same launch, against Verner 7 at 1e-12 with sensitivities.  The 99th
+    percentiles of eps^y (eq:st-fwderr) and eps^S (eq:st-graderr: rows
+    scaled by 1/r_E and 1/v_E, columns by v_c and q, Frobenius norms) must
+    meet the paper's budgets, 1e-4 and 1e-3 (eq:accept)."""
+    w = inputs.streams(n=10_000, seed=19)
+    prob = _prob(w)
+    g = to_np(api.solve(prob))
+    _, S, _ = api.solve_sens(prob, w["grad_cols"])
+    torch.cuda.synchronize()
+    S = S.cpu().numpy()                                     # [6][2][n]
+    ref = orc.solve(w["rhs"], "verner7", w["y0"], w["theta"], 0.0, w["t1"], 1e-12, 1e-12,
+                    sens_cols=w["grad_cols"])
+    v0, q, rc = w["theta"]
+    rE, vE = _orbit_scales(w["y0"], v0, q, rc)
+    dx = np.linalg.norm(g["y_final"][:3] - ref["y_final"][:3], axis=0) / rE
+    dv = np.linalg.norm(g["y_final"][3:] - ref["y_final"][3:], axis=0) / vE
+    eps_y = np.maximum(dx, dv)
+    Wrow = np.concatenate([np.broadcast_to(1 / rE, (3, rE.size)),
+                           np.broadcast_to(1 / vE, (3, vE.size))])[:, None, :]
+    Dcol = np.array([v0, q])[None, :, None]
+    num = np.linalg.norm((Wrow * (S - ref["S_final"]) * Dcol).reshape(12, -1), axis=0)
+    den = np.linalg.norm((Wrow * ref["S_final"] * Dcol).reshape(12, -1), axis=0)
+    eps_s = num / den
+    print(f"streams P99: eps_y {_p99(eps_y):.2e} (paper 5.7e-5), eps_S {_p99(eps_s):.2e} "
+          f"(paper 6e-4); mean attempts {(g['n_accepted'] + g['n_rejected']).mean():.1f}")
+    assert np.all(g["status"] == 0)
+    assert _p99(eps_y) <= 1e-4 and _p99(eps_s) <= 1e-3
+
+
 def _angle_error(a, b):
     """eq:prec-err: the largest angle between the final L, S1, S2 of two runs."""
     eps = np.zeros(a.shape[1])
