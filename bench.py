@@ -453,9 +453,64 @@ def main():
             if best is None or ms_g < best[1]:
                 best = (k, ms_g)
         log(f"[bench] gradient: forward {ms_fwd:.3f} ms, with tape + adjoint {per_k}")
+        # The plain arm: one lane per trajectory in both passes (static forward with the
+        # store-mode tape; an adjoint grid with exactly one lane for every trajectory).
+        cap1 = int(plain.n_accepted.max()) + 2
+        fused = api.Solution(pg, api.Launch(block=256, ckpt_every=1, ckpt_capacity=cap1))
+        stat = api.Solution(pg, api.Launch(schedule="static", block=256, ckpt_every=1,
+                                           ckpt_capacity=cap1))
+        ybf = torch.zeros((1, 6, pg.n), dtype=torch.float64, device="cuda")
+        grads = {}
+
+        def grad_of(sol, grid):
+            def step():
+                sol.run()
+                ybf[0, :3] = 2.0 * (sol.y_final[:3] - T)
+                grads[grid] = api.solve_vjp(sol, ybar_final=ybf, grid=grid)
+            return step
+
+        ms_stat = timed(grad_of(stat, (pg.n + 255) // 256), max(3, args.steps // 4), 1, torch)
+        ms_fused = timed(grad_of(fused, 0), max(3, args.steps // 4), 1, torch)
+        same = all(torch.equal(a, b) for a, b in zip(grads[0], grads[(pg.n + 255) // 256]))
+        log(f"[bench] gradient arms: fused persistent {ms_fused:.3f} ms, one lane per trajectory "
+            f"{ms_stat:.3f} ms, identical gradients {same}")
         out["grad"] = {"workload": "orbits_gradient_100k", "ms_forward": round(ms_fwd, 4),
                        "ms_forward_tape_plus_vjp": round(best[1], 4), "ckpt_every": best[0],
-                       "ms_by_ckpt_every": per_k}
+                       "ms_by_ckpt_every": per_k,
+                       "arms_ms": {"fused_persistent_store_tape": round(ms_fused, 4),
+                                   "one_lane_per_trajectory_store_tape": round(ms_stat, 4),
+                                   "identical_gradients": same}}
+        del fused, stat
+        # The same two arms on the uneven batch (lengths spread over two decades), where a
+        # wavefront of the plain arm waits for its longest trajectory in both passes.
+        nu = prob.n
+        cap_u = max_att // 32 + 2
+        ybu = torch.zeros((1, 6, nu), dtype=torch.float64, device="cuda")
+        Tu = torch.as_tensor(np.random.default_rng(8).normal(size=(3, nu)), device="cuda")
+        ugrads = {}
+
+        def ugrad_of(sol, grid):
+            def step():
+                sol.run()
+                ybu[0, :3] = 2.0 * (sol.y_final[:3] - Tu)
+                ugrads[grid] = api.solve_vjp(sol, ybar_final=ybu, grid=grid)
+            return step
+
+        ufused = api.Solution(prob, api.Launch(block=256, ckpt_every=32, ckpt_capacity=cap_u))
+        ufused.set_order(order)
+        ustat = api.Solution(prob, api.Launch(schedule="static", block=256, ckpt_every=32,
+                                              ckpt_capacity=cap_u))
+        ms_uf = timed(ugrad_of(ufused, 0), 3, 1, torch)
+        ms_us = timed(ugrad_of(ustat, (nu + 255) // 256), 3, 1, torch)
+        usame = all(torch.equal(a, b) for a, b in zip(ugrads[0], ugrads[(nu + 255) // 256]))
+        log(f"[bench] uneven-batch gradient arms (k = 32): fused persistent {ms_uf:.3f} ms, one "
+            f"lane per trajectory {ms_us:.3f} ms, identical gradients {usame}")
+        out["grad"]["uneven_batch_arms_ms"] = {
+            "workload": f"{nu} uneven orbits, checkpoints every 32 accepted steps, loss "
+                        "sum |x(t1) - T|^2",
+            "fused_persistent_longest_first": round(ms_uf, 4),
+            "one_lane_per_trajectory": round(ms_us, 4), "identical_gradients": usame}
+        del ufused, ustat
         out["grad_forward_ratio"] = best[1] / ms_fwd
         # The paper's own derivative: forward sensitivities in the same launch,
         # two columns (v0, q) as in its stream gradients, and all nine inputs.
