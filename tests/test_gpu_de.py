@@ -117,3 +117,35 @@ def test_profile_full_size(orc, spline):
     np.testing.assert_allclose(g["omega_m"][idx], o["om"], rtol=1e-9)
     np.testing.assert_allclose(g["h"][idx], o["h"], rtol=1e-9)
     np.testing.assert_allclose(g["chi2"][idx], o["chi2"], rtol=1e-7, atol=1e-9)
+
+
+@pytest.mark.parametrize("kd", [1, 12], ids=["one_point", "two_chunks"])
+def test_spline_data_counts(orc, kd):
+    """Data-point counts other than 7 through the spline: one point, and 12
+    (the Gauss-Newton kernel takes data points eight at a time) against the
+    oracle."""
+    from oracle import de_profile as de
+    w = inputs.de_profile_mocks(n_mocks=1, n_lambda=4)
+    s = dict(tableau=w["tableau"], t0=w["t0"], rtol=w["rtol"], atol=w["atol"])
+    orad = w["omega_r"]
+    N_data = np.sort(-np.log1p(np.random.default_rng(kd).uniform(0.1, 2.4, kd)))
+    w["nodes"], w["N_data"] = w["N_spline"], N_data
+    f = w["fid"]
+    lam1, om1 = np.array([f["lam"]]), np.array([f["om"]])
+    a0f = de.flat_amplitude(1.0 - om1 - orad, lam1, om1, orad, s, 4)
+    Dfid = de.at_data(de.model(a0f, lam1, om1, np.array([1.0]), orad, w["nodes"], s)[0],
+                      w["nodes"], N_data)[:, :, 0]
+    n = 4
+    noise = np.random.default_rng(kd + 1).normal(size=(2, kd, n))
+    data = Dfid[:, :, None] * (1.0 + 0.01 * noise)
+    sigma = 0.01 * Dfid
+    lam = w["lam_grid"]
+    om, h = np.full(n, 0.30), np.ones(n)
+    a0 = 1.0 - om - orad
+    g = _run_gpu(w, lam, om, h, a0, data, sigma)
+    o = _oracle(de, w, s, lam, om, h, a0, data, sigma)
+    assert np.all(g["status"] == 0)
+    for k in ("om", "h", "a0"):
+        np.testing.assert_allclose(g["omega_m" if k == "om" else k], o[k], rtol=1e-9, err_msg=k)
+    np.testing.assert_allclose(g["chi2"], o["chi2"], rtol=1e-7, atol=1e-9)
+    np.testing.assert_allclose(g["dist"], o["dist"], rtol=1e-9, atol=0)
