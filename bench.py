@@ -44,11 +44,18 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 PEAK_FP64_VECTOR_TFLOPS = 78.6   # MI355X: 256 CU x 2.4 GHz x 128 FP64 flop/clk
-# Algorithmic FP64 flops of one step attempt (fma = 2, div / sqrt / root = 1):
-#   Tsit5 stage sums 2 * 6 * (21 + 6) = 324, stage times 12, error weights
-#   2 * 6 * 7 + 6 = 90, norm 6 * 5 + 2 = 32, controller and clipping 5;
-#   log-halo right-hand side 13 per evaluation, 6 evaluations = 78.
-FLOPS_PER_ATTEMPT = {("tsit5", "loghalo"): 541, ("dopri5", "loghalo"): 535}
+# Algorithmic FP64 flops of one step attempt (fma = 2, div / sqrt / root / reciprocal = 1):
+#   stage sums 2 d (nnz(A) + s - 1), the update of a non-FSAL pair 2 d (nnz(b) + 1),
+#   stage times 2 (s - 1), error weights 2 d nnz(b - bhat) + d, norm 5 d + 2, controller
+#   and clipping 5, and one right-hand side per new stage (s - 1 for FSAL pairs, s else).
+#   Tsit5 + log halo (d 6, nnz(A) 21, nnz(e) 7, 13 per evaluation): 324 + 12 + 90 + 32 + 5
+#   + 78 = 541.  Dopri5 + log halo (nnz(A) 20, nnz(e) 6): 312 + 12 + 78 + 32 + 5 + 78 = 517.
+#   Verner 7 + precession (d 9, s 10, nnz(A) 36, nnz(b) 7, nnz(e) 8, 119 per evaluation):
+#   810 + 144 + 18 + 153 + 47 + 5 + 1190 = 2367; one output node (a shortened step) adds
+#   9 evaluations and the stage sums and update, 1071 + 810 + 144 = 2025.
+FLOPS_PER_ATTEMPT = {("tsit5", "loghalo"): 541, ("dopri5", "loghalo"): 517,
+                     ("verner7", "spinprec"): 2367}
+FLOPS_PER_NODE = {("verner7", "spinprec"): 2025}
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles",
                                "traffic_solve_kernel_tsit5_loghalo_orbits_uneven_100k.md")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2609_28458_amd", "csrc", f)
@@ -182,6 +189,32 @@ def stiff_bench(args, torch, api, inputs):
         log(f"[bench] stiff {w['rhs']} at 10^6: {ms:.3f} ms, {tf:.2f} TFLOP/s "
             f"({tf / 78.6:.1%})")
         del sol
+    return res
+
+
+def precession_showcase(torch, api, inputs):
+    """10^6 binaries from r = 1000 to 10, Verner 7 at 3.16e-9, 32 outputs: the
+    configuration whose work keeps every SIMD busy for seconds, timed once
+    after one warm-up run."""
+    w = inputs.spin_precession(n=1_000_000)
+    n = w["y0"].shape[1]
+    prob = api.make_problem(w["rhs"], w["tableau"], w["y0"], w["theta"], w["t0"], w["t1"],
+                            w["rtol"], w["atol"], w["t_out"])
+    sol = api.Solution(prob, api.Launch())
+    ms = timed(lambda: sol.run(), 1, 1, torch)
+    attempts = int((sol.n_accepted.to(torch.int64) + sol.n_rejected).sum())
+    flops = (attempts * FLOPS_PER_ATTEMPT[("verner7", "spinprec")]
+             + n * prob.K * FLOPS_PER_NODE[("verner7", "spinprec")])
+    tf = flops / (ms * 1e-3) / 1e12
+    res = {"workload": f"{n} binaries, r = 1000 -> 10, Verner 7 3.16e-9, {prob.K} outputs",
+           "ms": round(ms, 2), "attempts": attempts,
+           "flops_per_attempt": FLOPS_PER_ATTEMPT[("verner7", "spinprec")],
+           "achieved": round(tf, 3), "peak": PEAK_FP64_VECTOR_TFLOPS, "unit": "TFLOP/s",
+           "frac": round(tf / PEAK_FP64_VECTOR_TFLOPS, 4),
+           "all_ok": bool((sol.status == 0).all())}
+    log(f"[bench] precession showcase: {ms:.1f} ms, {attempts} attempts, {tf:.2f} TFLOP/s "
+        f"({tf / PEAK_FP64_VECTOR_TFLOPS:.1%})")
+    del sol
     return res
 
 
@@ -576,6 +609,10 @@ def main():
     # ---- stiff path: Rodas4 on 10^5 trajectories of each kinetics network --------------------
     if not args.no_grad:
         out["stiff"] = stiff_bench(args, torch, api, inputs)
+
+    # ---- the precession configuration at full size: the chip full for seconds --------------
+    if not args.no_grad:
+        out["roofline_showcase"] = precession_showcase(torch, api, inputs)
 
     # ---- the paper's own per-trajectory workloads at 10^6 (its H200 figures as context) -------
     if not args.no_grad:
