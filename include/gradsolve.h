@@ -40,7 +40,7 @@ extern "C" {
 typedef enum gs_status {
   GS_OK = 0,
   GS_ERR_INVALID = 1,     /* bad argument (null pointer, size, layout, order) */
-  GS_ERR_UNSUPPORTED = 2, /* valid request this build does not implement     */
+  GS_ERR_UNSUPPORTED = 2, /* valid request the library does not implement    */
   GS_ERR_WORKSPACE = 3,   /* workspace missing or smaller than required      */
   GS_ERR_HIP = 4,         /* a HIP runtime call failed                       */
   GS_ERR_NO_TAPE = 5      /* gradient requested but the solve kept no tape   */
