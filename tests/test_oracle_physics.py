@@ -247,3 +247,24 @@ def test_precession_matches_paper_accuracy_and_cost(orc):
                       (tl, g["tsit5_looser_p99_rad"])):
         assert abs(got / want - 1) < 0.15, (got, want)
     assert v < g["budget_rad"] and t < g["budget_rad"] < tl
+
+
+def test_stream_recipe_matches_the_papers_attempt_count(orc):
+    """The stream orbits of inputs.streams take, on the oracle, the mean
+    number of Tsit5 attempts the paper prints for its stream ensemble at
+    3.16e-7 (171), within 3%; every orbit conserves its energy to the
+    tolerance's order."""
+    from paper_2609_28458_amd import inputs
+    w = inputs.streams(n=3000, seed=9)
+    o = orc.solve(w["rhs"], w["tableau"], w["y0"], w["theta"], w["t0"], w["t1"], w["rtol"],
+                  w["atol"])
+    assert np.all(o["status"] == 0)
+    mean = float((o["n_accepted"] + o["n_rejected"]).mean())
+    assert abs(mean - 171.0) < 0.03 * 171.0, mean
+    v0, q, rc = w["theta"]
+
+    def energy(y):
+        Dn = rc * rc + y[0] ** 2 + y[1] ** 2 + y[2] ** 2 / q ** 2
+        return 0.5 * (y[3] ** 2 + y[4] ** 2 + y[5] ** 2) + 0.5 * v0 * v0 * np.log(Dn)
+
+    assert np.max(np.abs(energy(o["y_final"]) - energy(w["y0"]))) < 1e-4
