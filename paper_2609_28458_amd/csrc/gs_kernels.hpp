@@ -869,6 +869,7 @@ __device__ __forceinline__ void forward_body(const Params& P, const SensParams& 
   Traj<TB, F, T> s;
   int64_t idx = -1;
   int32_t kp = 0;
+  double t_next = 0.0;  // time of output node kp, kept in a register (infinity after the last)
   bool live = false, overflow = false;
   bool queue_empty = P.sched_static != 0;  // wave-uniform
   const int lane = threadIdx.x & 63;
@@ -942,6 +943,7 @@ __device__ __forceinline__ void forward_body(const Params& P, const SensParams& 
       put_node(kp, s.y);
       ++kp;
     }
+    if constexpr (NODES) t_next = kp < P.K ? node_time(P, kp, i) : __builtin_inf();
     if (!fin) {
       finish(ST_NONFINITE);
       return;
@@ -1009,9 +1011,10 @@ __device__ __forceinline__ void forward_body(const Params& P, const SensParams& 
           const Attempt a = attempt<TB, F>(
               P, s, [&](const Traj<TB, F, T>& sa, double t_old, double hh, const T (&ys)[D]) {
                 if constexpr (!NODES) return;
-                while (kp < P.K) {
-                  const double tq = node_time(P, kp, idx);
-                  if (!(tq <= sa.t)) break;
+                // the next output time sits in a register: memory is read only
+                // when an output is passed, not on every accepted step
+                while (t_next <= sa.t) {
+                  const double tq = t_next;
                   if (tq == sa.t) {
                     put_node(kp, sa.y);
                   } else {
@@ -1021,6 +1024,7 @@ __device__ __forceinline__ void forward_body(const Params& P, const SensParams& 
                     put_node(kp, out);
                   }
                   ++kp;
+                  t_next = kp < P.K ? node_time(P, kp, idx) : __builtin_inf();
                 }
               });
           if constexpr (!TAPE) {
@@ -1215,6 +1219,7 @@ __global__ void __launch_bounds__(256) vjp_kernel(Params P, VjpParams V) {
   bool live = false, ok = false;
   bool queue_empty = false;  // wave-uniform
   int32_t N = 0, cseg = -1, kp = -1;
+  double t_kp = -__builtin_inf();  // time of output node kp, kept in a register
 
   auto gbar = [&](int r, int c, int kk) -> double {
     return (V.ybar_out && r < V.R)
@@ -1256,6 +1261,7 @@ __global__ void __launch_bounds__(256) vjp_kernel(Params P, VjpParams V) {
       for (int c = 0; c < NP; ++c) THB(r, c) = 0.0;
     }
     kp = P.K - 1;
+    if constexpr (NODES) t_kp = kp >= 0 ? node_time(P, kp, i) : -__builtin_inf();
     cseg = (N + kseg - 1) / kseg - 1;
     if (!ok || cseg < 0) finish();
   };
@@ -1384,16 +1390,22 @@ __global__ void __launch_bounds__(256) vjp_kernel(Params P, VjpParams V) {
         reverse_step<TB, F, R>(s.in, tn, hn, yn, lam, thb, false, no_seed, ysc, ys);
       } else {
         // Nodes at the end of the step read y+ itself.
-        while (kp >= 0 && node_time(P, kp, idx) == t_new) {
+        // (node times are read from memory only when a node is passed)
+        while (kp >= 0 && t_kp == t_new) {
 #pragma unroll
           for (int r = 0; r < R; ++r)
 #pragma unroll
             for (int c = 0; c < D; ++c) lam[r][c] += gbar(r, c, kp);
           --kp;
+          t_kp = kp >= 0 ? node_time(P, kp, idx) : -__builtin_inf();
         }
         // Nodes inside the step: indices kp, kp - 1, ..., k_lo + 1.
         int k_lo = kp;
-        while (k_lo >= 0 && node_time(P, k_lo, idx) > tn) --k_lo;
+        double t_lo = t_kp;
+        while (k_lo >= 0 && t_lo > tn) {
+          --k_lo;
+          t_lo = k_lo >= 0 ? node_time(P, k_lo, idx) : -__builtin_inf();
+        }
         if constexpr (TB::POLY_DENSE) {
           // All of them enter one reverse pass: their cotangents are linear
           // seeds of the stages, added while the stage cotangents are set
@@ -1423,6 +1435,7 @@ __global__ void __launch_bounds__(256) vjp_kernel(Params P, VjpParams V) {
           };
           reverse_step<TB, F, R>(s.in, tn, hn, yn, lam, thb, any, seed, ysc, ys);
           kp = k_lo;
+          t_kp = t_lo;
         } else {
           // Shortened-step outputs: each is a full step of length sigma h
           // from y_n with its own stage points, so each takes a reverse pass
@@ -1453,6 +1466,7 @@ __global__ void __launch_bounds__(256) vjp_kernel(Params P, VjpParams V) {
               }
             kp -= has ? 1 : 0;
           } while (has);
+          t_kp = t_lo;  // kp == k_lo here
         }
       }
     }

@@ -331,6 +331,7 @@ stiff_kernel(Params P) {
   Inputs<F> in;
   double y[D], f0[D];
   double t = 0.0, h = 0.0;
+  double t_stop = 0.0;  // the next output time, or t1 after the last (in a register)
   int32_t nacc = 0, nrej = 0, nanrun = 0, kk = 0;
 
   auto store_node = [&](int q, const double (&v)[D]) {
@@ -365,6 +366,7 @@ stiff_kernel(Params P) {
       return;
     }
     while (kk < P.K && node_time(P, kk, i) <= in.t0) store_node(kk++, y);
+    t_stop = kk < P.K ? node_time(P, kk, i) : in.t1;
     if (!fin) {
       finish(ST_NONFINITE);
       return;
@@ -409,7 +411,7 @@ stiff_kernel(Params P) {
         if ((int64_t)nacc + nrej >= P.max_steps) {
           st = ST_MAX_STEPS;
         } else {
-          const double stop = kk < P.K ? node_time(P, kk, idx) : in.t1;
+          const double stop = t_stop;
           double hh = h;
           bool land = false;
           if (t + hh >= stop) {
@@ -433,7 +435,10 @@ stiff_kernel(Params P) {
             if (!yfin) {
               st = ST_NONFINITE;
             } else {
-              while (kk < P.K && node_time(P, kk, idx) <= t) store_node(kk++, y);
+              while (kk < P.K && t_stop <= t) {
+                store_node(kk++, y);
+                t_stop = kk < P.K ? node_time(P, kk, idx) : in.t1;
+              }
               F::f(t, y, in.par, f0);
               nanrun = 0;
               done = t >= in.t1;
