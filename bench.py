@@ -218,6 +218,46 @@ def precession_showcase(torch, api, inputs):
     return res
 
 
+def precession_gradient(torch, api, inputs):
+    """Gradients of both final tilt angles with respect to (q, chi1, chi2) for
+    2x10^4 binaries from r = 1000: the forward solve alone, the forward with a
+    checkpoint tape plus one adjoint launch per loss, and the paper's own
+    route, forward sensitivities of the three parameters."""
+    w = inputs.spin_precession(n=20_000)
+    n = w["y0"].shape[1]
+    prob = api.make_problem(w["rhs"], w["tableau"], w["y0"], w["theta"], w["t0"], w["t1"],
+                            w["rtol"], w["atol"])
+    plain = api.Solution(prob, api.Launch())
+    ms_f = timed(lambda: plain.run(), 2, 1, torch)
+    cap = int(plain.n_accepted.max()) // 128 + 2
+    sol = api.Solution(prob, api.Launch(ckpt_every=128, ckpt_capacity=cap))
+    # cotangents of the two tilt angles at the (deterministic) final state, once
+    sol.run()
+    y = sol.y_final.detach().clone().requires_grad_(True)
+    ybar = torch.zeros((2, 9, n), dtype=torch.float64, device="cuda")
+    for r, s0 in enumerate((3, 6)):
+        a, b = y[0:3], y[s0:s0 + 3]
+        ang = torch.atan2(torch.linalg.norm(torch.cross(a, b, dim=0), dim=0), (a * b).sum(0))
+        (ybar[r],) = torch.autograd.grad(ang.sum(), y)
+
+    def tilt_grads():
+        sol.run()
+        return api.solve_vjp(sol, ybar_final=ybar)
+
+    ms_g = timed(tilt_grads, 2, 1, torch)
+    ms_s = timed(lambda: api.solve_sens(prob, [9, 10, 11]), 2, 1, torch)
+    res = {"workload": f"{n} binaries, r = 1000 -> 10, Verner 7 3.16e-9, losses: both final "
+                       "tilt angles, parameters (q, chi1, chi2)",
+           "ms_forward": round(ms_f, 2),
+           "ms_tape_k128_plus_two_adjoints": round(ms_g, 2),
+           "ratio_adjoint": round(ms_g / ms_f, 3),
+           "ms_forward_sensitivities_3_columns": round(ms_s, 2),
+           "ratio_forward_sensitivities": round(ms_s / ms_f, 3)}
+    log(f"[bench] precession gradient: {json.dumps(res)}")
+    del plain, sol
+    return res
+
+
 def paper_workloads(torch, api, inputs, autotune):
     """Microseconds per trajectory on the paper's three ensembles at 10^6
     trajectories, beside the figures the paper prints for one H200 NVL
@@ -613,6 +653,7 @@ def main():
     # ---- the precession configuration at full size: the chip full for seconds --------------
     if not args.no_grad:
         out["roofline_showcase"] = precession_showcase(torch, api, inputs)
+        out["precession_gradient"] = precession_gradient(torch, api, inputs)
 
     # ---- the paper's own per-trajectory workloads at 10^6 (its H200 figures as context) -------
     if not args.no_grad:
