@@ -245,12 +245,21 @@ def precession_gradient(torch, api, inputs):
         return api.solve_vjp(sol, ybar_final=ybar)
 
     ms_g = timed(tilt_grads, 2, 1, torch)
+    del sol
+    # store mode: every accepted step on the tape (tens of GB here), no replay
+    sol = api.Solution(prob, api.Launch(ckpt_every=1,
+                                        ckpt_capacity=int(plain.n_accepted.max()) + 2))
+    tape_gb = sol.workspace.numel() / 1e9
+    ms_st = timed(tilt_grads, 2, 1, torch)
     ms_s = timed(lambda: api.solve_sens(prob, [9, 10, 11]), 2, 1, torch)
     res = {"workload": f"{n} binaries, r = 1000 -> 10, Verner 7 3.16e-9, losses: both final "
                        "tilt angles, parameters (q, chi1, chi2)",
            "ms_forward": round(ms_f, 2),
            "ms_tape_k128_plus_two_adjoints": round(ms_g, 2),
            "ratio_adjoint": round(ms_g / ms_f, 3),
+           "ms_store_tape_plus_two_adjoints": round(ms_st, 2),
+           "store_tape_gb": round(tape_gb, 1),
+           "ratio_adjoint_store": round(ms_st / ms_f, 3),
            "ms_forward_sensitivities_3_columns": round(ms_s, 2),
            "ratio_forward_sensitivities": round(ms_s / ms_f, 3)}
     log(f"[bench] precession gradient: {json.dumps(res)}")
