@@ -244,14 +244,14 @@ def precession_gradient(torch, api, inputs):
         sol.run()
         return api.solve_vjp(sol, ybar_final=ybar)
 
-    ms_g = timed(tilt_grads, 2, 1, torch)
+    ms_g = timed(tilt_grads, 1, 1, torch)
     del sol
     # store mode: every accepted step on the tape (tens of GB here), no replay
     sol = api.Solution(prob, api.Launch(ckpt_every=1,
                                         ckpt_capacity=int(plain.n_accepted.max()) + 2))
     tape_gb = sol.workspace.numel() / 1e9
-    ms_st = timed(tilt_grads, 2, 1, torch)
-    ms_s = timed(lambda: api.solve_sens(prob, [9, 10, 11]), 2, 1, torch)
+    ms_st = timed(tilt_grads, 1, 1, torch)
+    ms_s = timed(lambda: api.solve_sens(prob, [9, 10, 11]), 1, 1, torch)
     res = {"workload": f"{n} binaries, r = 1000 -> 10, Verner 7 3.16e-9, losses: both final "
                        "tilt angles, parameters (q, chi1, chi2)",
            "ms_forward": round(ms_f, 2),
