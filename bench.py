@@ -138,7 +138,7 @@ def rodas4_flops_per_attempt(D, jac_flops, rhs_flops):
             + 17 * D + 1)
 
 
-def stiff_bench(args, torch, api, inputs):
+def stiff_bench(args, torch, api, inputs, autotune):
     """Rodas4 kernel on the two stiff kinetics workloads (10^5 trajectories,
     16 output times each), graph-launched, with the oracle on a seeded sample
     of the host's cores for scale."""
@@ -150,7 +150,7 @@ def stiff_bench(args, torch, api, inputs):
         w = gen()
         prob = api.make_problem(w["rhs"], w["tableau"], w["y0"], w["theta"], w["t0"], w["t1"],
                                 w["rtol"], w["atol"], w["t_out"])
-        sol = api.Solution(prob, api.Launch())
+        sol = api.Solution(prob, autotune.tune_forward(prob, use_cache=False))
         graph = api.Graph(sol)
         ms = timed(lambda: graph.launch(), max(5, args.steps // 2), 2, torch)
         torch.cuda.synchronize()
@@ -170,7 +170,8 @@ def stiff_bench(args, torch, api, inputs):
             "solves_per_s": n / (ms * 1e-3), "attempts": attempts, "all_ok": ok,
             "roofline": {"bound": "alu", "flops_per_attempt": fpa, "achieved": round(tf, 3),
                          "peak": 78.6, "unit": "TFLOP/s", "frac": round(tf / 78.6, 4)},
-            "cpu_oracle_solves_per_s": round(cpu, 1), "cpu_threads": threads}
+            "cpu_oracle_solves_per_s": round(cpu, 1), "cpu_threads": threads,
+            "launch": {k: sol.launch.__dict__[k] for k in ("block", "grid", "refill")}}
         log(f"[bench] stiff {w['rhs']}: {ms:.3f} ms, {n / ms * 1e3:.3e} solves/s, "
             f"{tf:.2f} TFLOP/s ({tf / 78.6:.1%} of FP64 peak); oracle {cpu:.0f} solves/s")
         graph.close()
@@ -179,7 +180,7 @@ def stiff_bench(args, torch, api, inputs):
         w = gen(n=1_000_000, K=0)
         prob = api.make_problem(w["rhs"], w["tableau"], w["y0"], w["theta"], w["t0"], w["t1"],
                                 w["rtol"], w["atol"])
-        sol = api.Solution(prob, api.Launch())
+        sol = api.Solution(prob, autotune.tune_forward(prob, use_cache=False))
         ms = timed(lambda: sol.run(), 3, 1, torch)
         attempts = int((sol.n_accepted.to(torch.int64) + sol.n_rejected).sum())
         tf = fpa * attempts / (ms * 1e-3) / 1e12
@@ -657,7 +658,7 @@ def main():
 
     # ---- stiff path: Rodas4 on 10^5 trajectories of each kinetics network --------------------
     if not args.no_grad:
-        out["stiff"] = stiff_bench(args, torch, api, inputs)
+        out["stiff"] = stiff_bench(args, torch, api, inputs, autotune)
 
     # ---- the precession configuration at full size: the chip full for seconds --------------
     if not args.no_grad:

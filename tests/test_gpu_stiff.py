@@ -152,3 +152,19 @@ def test_full_size_sampled(orc, gen):
     _compare(g, _oracle(orc, w, idx), idx)
     print(f"{w['rhs']}: mean accepted {g['n_accepted'].mean():.1f}, "
           f"max {g['n_accepted'].max()}, mean rejected {g['n_rejected'].mean():.2f}")
+
+
+def test_shared_parameters_and_output_times(orc):
+    """theta as one shared vector (stride 0) and one shared set of output
+    times [K]: the same results as the per-trajectory layouts holding the
+    same values, and parity with the oracle."""
+    w = inputs.kinetics3(n=300, seed=28)
+    th = w["theta"][:, 0].copy()
+    t_out = np.logspace(-4, 1, 12)
+    shared = dict(w, theta=th, t1=np.full(300, 10.0), t_out=t_out)
+    spread = dict(w, theta=np.repeat(th[:, None], 300, axis=1), t1=np.full(300, 10.0),
+                  t_out=np.repeat(t_out[:, None], 300, axis=1))
+    a, b = _gpu_solve(shared), _gpu_solve(spread)
+    for k in a:
+        np.testing.assert_array_equal(a[k], b[k], err_msg=k)
+    _compare(a, _oracle(orc, shared))
