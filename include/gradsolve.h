@@ -283,7 +283,7 @@ gs_status gs_solve_sens(const gs_solve_args* args, const gs_sens_args* sens);
  * allocates nothing (workspace: gs_de_profile_workspace_bytes, 256-byte
  * aligned) and only enqueues work on `stream`. */
 typedef struct gs_de_profile_args {
-  int64_t n;                /* minimisations                                */
+  int64_t n;                /* minimisations, <= 2^31                       */
   const double* lambda;     /* [n] fixed slope                              */
   double* omega_m;          /* [n] in: start; out: fitted                   */
   double* h;                /* [n] in: start; out: fitted                   */

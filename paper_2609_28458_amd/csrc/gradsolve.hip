@@ -451,6 +451,7 @@ gs_status gs_de_profile(const gs_de_profile_args* A) {
   if (!A || A->n < 0 || A->K < 1 || A->iters < 0 || A->newton < 0 || A->K_data < 0)
     return GS_ERR_INVALID;
   if (A->K_data > 0 && (A->K < 4 || !A->N_data)) return GS_ERR_INVALID;
+  if (A->n > (int64_t)1 << 31) return GS_ERR_UNSUPPORTED;  // grid sizes are int
   if (A->tableau < 0 || A->tableau >= kNumExplicitTab || !(A->rtol > 0.0) || !(A->atol >= 0.0) ||
       !(A->N_start < 0.0) || !(A->mu >= 0.0) || !(A->trust_om > 0.0) || !(A->trust_h > 0.0))
     return GS_ERR_INVALID;
@@ -575,6 +576,7 @@ gs_status gs_rhs_eval(int32_t rhs, int64_t m, const double* t, const double* y,
                       const double* theta, double* f, const double* kbar, double* ybar,
                       double* thetabar, void* stream) {
   if (rhs < 0 || rhs >= kNumRhs || m < 0) return GS_ERR_INVALID;
+  if (m > (int64_t)1 << 31) return GS_ERR_UNSUPPORTED;  // grid sizes are int
   if (m == 0) return GS_OK;
   if (!t || !y || !theta) return GS_ERR_INVALID;
   const bool want_vjp = kbar || ybar || thetabar;

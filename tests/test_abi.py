@@ -184,3 +184,11 @@ def test_stiff_path_argument_checks():
     assert L.gs_rhs_eval(5, 10, 0x1000, 0x1000, 0x1000, 0x1000, 0x1000, 0x1000, 0x1000,
                          None) == 2
     assert L.gs_rhs_eval(7, 10, 0x1000, 0x1000, 0x1000, 0x1000, None, None, None, None) == 1
+
+
+def test_size_limits():
+    L = api.lib()
+    assert L.gs_de_profile(C.byref(_de_args(n=(1 << 31) + 1, workspace_bytes=1 << 40))) == 2
+    assert L.gs_rhs_eval(2, (1 << 31) + 1, 0x1000, 0x1000, 0x1000, 0x1000, None, None, None,
+                         None) == 2
+    assert L.gs_solve(C.byref(_args(n=(1 << 31) + 1))) == 2
