@@ -13,8 +13,9 @@ Also reported on the same line:
   * roofline of the solve kernel: algorithmic FP64 flops per launch over its
     duration (HIP events on the launch stream) against the FP64 vector peak,
     HBM traffic from the committed PMC summary when it matches the kernel
-    source, and the critical-path bound of this batch (its longest orbit's
-    attempts times the measured time of one attempt of a lone wavefront);
+    source, and the critical-path bound of this batch (its longest orbit
+    solved alone, on one lane and on one 16-lane group: the faster of the
+    two);
   * the same kernel at full occupancy (10^6 uniform orbits) for comparison;
   * the two other launch arms of the batch (static one lane per trajectory,
     one launch per cost bucket);
@@ -363,6 +364,15 @@ def headline(args, torch, api, inputs, autotune):
     return w, prob, order
 
 
+def profile_launch(torch, api):
+    """The headline's launch shape as the autotuner picks it on MI355X (one
+    wavefront per workgroup and per SIMD, refill at one idle lane, the 2048
+    predicted-longest orbits on 16-lane groups), fixed for the profiling
+    modes."""
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    return api.Launch(schedule="queue", block=64, grid=4 * cus, refill=1, wide=2048)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -385,7 +395,7 @@ def main():
         b = torch.empty_like(a)
         torch.cuda.synchronize()
         b.copy_(a)
-        sol = api.Solution(prob, api.Launch(block=256))
+        sol = api.Solution(prob, profile_launch(torch, api))
         sol.set_order(order)
         sol.run()
         torch.cuda.synchronize()
@@ -396,7 +406,7 @@ def main():
     if args.mode == "full":
         launch = autotune.tune_forward(prob, order=order, use_cache=False)
     else:
-        launch = api.Launch(schedule="queue", block=256, refill=16)
+        launch = profile_launch(torch, api)
     sol = api.Solution(prob, launch)
     sol.set_order(order)
     graph = api.Graph(sol)
@@ -424,16 +434,22 @@ def main():
     fpa = FLOPS_PER_ATTEMPT[("tsit5", "loghalo")]
     achieved = attempts * fpa / (ms_kernel * 1e-3) / 1e12
 
-    # One wavefront alone: the time of one attempt on the critical path.
-    lw = dict(w)
-    lw.update(y0=w["y0"][:, :64], theta=w["theta"][:, :64], t1=np.full(64, 300.0),
-              rtol=np.full(64, 1e-9), atol=np.full(64, 1e-9))
-    lprob = api.make_problem(lw["rhs"], lw["tableau"], lw["y0"], lw["theta"], 0.0, lw["t1"],
-                             lw["rtol"], lw["atol"])
+    # The critical path: the longest orbit of the batch alone, on one lane
+    # and on one 16-lane group.  No launch shape finishes the batch before
+    # that orbit has run all of its attempts in the faster of the two modes.
+    i_long = int(torch.argmax(sol.n_accepted + sol.n_rejected))
+    one = {k: (v[..., [i_long]] if isinstance(v, np.ndarray) and v.shape[-1:] == (n,) else v)
+           for k, v in w.items()}
+    lprob = api.make_problem(one["rhs"], one["tableau"], one["y0"], one["theta"], one["t0"],
+                             one["t1"], one["rtol"], one["atol"])
     lsol = api.Solution(lprob, api.Launch(block=64))
     ms_lone = timed(lambda: lsol.run(), 3, 1, torch)
-    us_per_attempt = ms_lone * 1e3 / int((lsol.n_accepted + lsol.n_rejected).max())
-    bound_ms = max_att * us_per_attempt * 1e-3
+    us_per_attempt = ms_lone * 1e3 / max_att
+    gsol = api.Solution(lprob, api.Launch(block=64, wide=1))
+    ms_group = timed(lambda: gsol.run(), 3, 1, torch)
+    us_group = ms_group * 1e3 / max_att
+    assert int((gsol.n_accepted + gsol.n_rejected).item()) == max_att
+    bound_ms = min(ms_lone, ms_group)
 
     traffic, traffic_src = committed_traffic()
     roofline = {"bound": "alu", "achieved": round(achieved, 3),
@@ -444,7 +460,10 @@ def main():
                 "flops_per_attempt": fpa, "attempts_per_launch": attempts,
                 "ms_per_launch": round(ms_kernel, 4),
                 "critical_path": {"max_attempts_one_orbit": max_att,
+                                  "longest_orbit_alone_ms": {"one_lane": round(ms_lone, 3),
+                                                             "group": round(ms_group, 3)},
                                   "lone_wave_us_per_attempt": round(us_per_attempt, 4),
+                                  "lone_group_us_per_attempt": round(us_group, 4),
                                   "bound_ms": round(bound_ms, 3),
                                   "frac_of_bound": round(bound_ms / ms_kernel, 3)}}
 
@@ -462,7 +481,8 @@ def main():
                   "ms": round(ms_t, 3), "attempts": att_t, "achieved": round(ach_t, 3),
                   "unit": "TFLOP/s", "frac": round(ach_t / PEAK_FP64_VECTOR_TFLOPS, 4)}
     log(f"[bench] kernel {ms_kernel:.3f} ms = {achieved:.2f} TFLOP/s; lone wave "
-        f"{us_per_attempt:.3f} us/attempt -> bound {bound_ms:.2f} ms; full chip "
+        f"{us_per_attempt:.3f} us/attempt, lone group {us_group:.3f} us/attempt -> bound "
+        f"{bound_ms:.2f} ms; full chip "
         f"{ach_t:.2f} TFLOP/s")
 
     out = {

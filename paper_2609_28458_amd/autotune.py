@@ -3,7 +3,8 @@
 For a problem class (right-hand side, tableau, log2 of the ensemble size,
 device) it times candidate launch shapes of the forward kernel -- lanes per
 workgroup, persistent-grid size (one or two wavefronts per SIMD, or the full
-occupancy limit), refill granularity of the work queue -- and, for gradient
+occupancy limit), refill granularity of the work queue, how many trajectories
+at the head of a longest-first order run on 16-lane groups -- and, for gradient
 runs, the checkpoint interval k of the tape (forward with tape plus adjoint).
 The fastest shape is cached in a JSON file keyed by problem class.  Timing
 uses HIP events on the stream the kernels run on.
@@ -23,6 +24,10 @@ CACHE = os.environ.get("GS_AUTOTUNE_CACHE",
 
 BLOCKS = (64, 128, 256)
 REFILLS = (1, 4, 8, 16, 64)
+# Trajectories at the head of the queue order run on 16-lane groups (wide):
+# tried on the best shapes when the call allows it (queue schedule, no
+# output nodes, no tape, at most 16 state components).
+WIDES = (1024, 2048, 4096, 8192)
 CKPT = (1, 8, 32, 128)  # 1 = store mode: every accepted step on the tape
 
 
@@ -84,12 +89,24 @@ def tune_forward(prob: api.Problem, order=None, base: api.Launch | None = None,
     for block in BLOCKS:
         for grid in _grids(prob, block):
             for refill in REFILLS:
-                shape = {"schedule": "queue", "block": block, "grid": grid, "refill": refill}
+                shape = {"schedule": "queue", "block": block, "grid": grid, "refill": refill,
+                         "wide": 0}
                 sol = api.Solution(prob, api.Launch(**{**base.__dict__, **shape}))
                 if order is not None:
                     sol.set_order(order)
                 scored.append((_time(lambda: sol.run()), shape))
     scored.sort(key=lambda x: x[0])
+    if (order is not None and prob.K == 0 and base.ckpt_every == 0 and prob.d <= 16
+            and prob.tableau != api.TABLEAU["rodas4"]):
+        for _, shape0 in scored[:3]:
+            for wide in WIDES:
+                if wide >= prob.n:
+                    continue
+                shape = {**shape0, "wide": wide}
+                sol = api.Solution(prob, api.Launch(**{**base.__dict__, **shape}))
+                sol.set_order(order)
+                scored.append((_time(lambda: sol.run()), shape))
+        scored.sort(key=lambda x: x[0])
     finalists = []
     for _, shape in scored[:4]:
         sol = api.Solution(prob, api.Launch(**{**base.__dict__, **shape}))

@@ -582,16 +582,22 @@ struct FwdOccupancy {
 // a sixth of the stage arithmetic on the critical path of one trajectory.
 constexpr int kGroup = 16;
 
+// A DPP move of a double within each row of 16 lanes.  Lanes whose source
+// lies outside the row read 0 (bound_ctrl); no old value is kept, so no
+// register is cleared first.  Callers run it with every lane of the row
+// active (DPP is convergent: the compiler keeps it out of divergent code).
 template <int CTRL>
 __device__ __forceinline__ double dpp_mov(double v) {
-  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xF, 0xF, true);
   return __hiloint2double(hi, lo);
 }
-// Lane SRC of this lane's row, in every lane of the row (row_newbcast).
+// Lane SRC of this lane's row, in every lane of the row (row_newbcast, the
+// one DPP control that moves 64 bits in one instruction on this chip).
 template <int SRC>
 __device__ __forceinline__ double row_bcast(double v) {
-  return dpp_mov<0x150 + SRC>(v);
+  return __longlong_as_double(
+      __builtin_amdgcn_mov_dpp(__double_as_longlong(v), 0x150 + SRC, 0xF, 0xF, true));
 }
 // Sum over the 16 lanes of the row: partners l^1, l^2 (quad_perm), then the
 // other quad of the half-row (row_half_mirror), then the other half-row
@@ -626,6 +632,79 @@ __device__ __forceinline__ double pick(const double (&v)[D], int c) {
   return __longlong_as_double((long long)r);
 }
 
+// Component c of f(t, Y) for the row whose lane c holds Y[c]: the full
+// vector is gathered, every lane evaluates the right-hand side and keeps its
+// component; lanes c >= D get 0.
+template <class F>
+struct RowRhs {
+  __device__ static double f(double t, double yc, const typename F::Par& p, int c) {
+    double Y[F::D], kf[F::D];
+    row_gather<F::D>(yc, Y);
+    F::f(t, Y, p, kf);
+    return c < F::D ? pick<F::D>(kf, c) : 0.0;
+  }
+};
+
+// The logarithmic halo (eq:loghalo) written per component: the positions
+// are broadcast for the denominator, lane c < 3 takes the velocity from lane
+// c + 3 (row_shl:3) and lane 3 <= c < 6 its position from lane c - 3
+// (row_shr:3), times the lane's weight (1, 1, 1/q^2 for c = 3, 4, 5; 0
+// beyond, so lanes c >= 6 get 0 while the state is finite).  The weight
+// depends only on the lane and the parameters, so the compiler keeps it out
+// of the attempt loop.  Every expression and its order are those of
+// LogHalo::f (1 * x is exact), so the result is bit-identical to component
+// c of the full evaluation.
+template <>
+struct RowRhs<LogHalo> {
+  __device__ static double f(double, double yc, const LogHalo::Par& p, int c) {
+    const double x = row_bcast<0>(yc), y = row_bcast<1>(yc), z = row_bcast<2>(yc);
+    const double vel = dpp_mov<0x103>(yc);
+    const double pos = dpp_mov<0x113>(yc);
+    const double Dn = fma(z * z, p.iq2, fma(y, y, fma(x, x, p.rc2)));
+    const double s = -p.v02 * fast_rcp(Dn);
+    const double w = c == 5 ? p.iq2 : (c < 6 ? 1.0 : 0.0);
+    return c < 3 ? vel : s * (w * pos);
+  }
+};
+
+// The tableau's coefficients in vector registers for the group loop.  As
+// immediates every 64-bit coefficient costs two scalar moves per use inside
+// the loop (the compiler rematerialises them rather than keep 60+ scalar
+// registers), and each scalar move takes an issue slot of the wavefront on
+// the critical path.  Passing each value once through an empty asm statement
+// with a VGPR constraint hides that it is a constant, so it is loaded before
+// the loop and stays in a VGPR; the values, and so the results, are the
+// tableau's own.  Entries that the tableau has as zero are never read.
+template <class TB>
+struct GroupCoef {
+  double a[TB::S][TB::S], b[TB::S], e[TB::S], c[TB::S];
+  __device__ __forceinline__ void load() {
+    sfor<TB::S>([&](auto J) {
+      constexpr int j = decltype(J)::value;
+      sfor<TB::S>([&](auto L) {
+        constexpr int l = decltype(L)::value;
+        if constexpr (l < j && TB::A(j, l) != 0.0) a[j][l] = hold(TB::A(j, l));
+      });
+      if constexpr (TB::B(j) != 0.0) b[j] = hold(TB::B(j));
+      if constexpr (TB::E(j) != 0.0) e[j] = hold(TB::E(j));
+      if constexpr (TB::C(j) != 0.0) c[j] = hold(TB::C(j));
+    });
+  }
+  // Node j of the stage times (0 where the tableau has 0).
+  template <int j>
+  __device__ __forceinline__ double node() const {
+    if constexpr (TB::C(j) != 0.0) {
+      return c[j];
+    } else {
+      return 0.0;
+    }
+  }
+  __device__ static __forceinline__ double hold(double v) {
+    asm("" : "+v"(v));
+    return v;
+  }
+};
+
 template <class TB, class F>
 struct GroupTraj {
   static constexpr int S = TB::S, D = F::D;
@@ -638,7 +717,8 @@ struct GroupTraj {
 
 // One attempt of a group: the single-lane attempt() component by component.
 template <class TB, class F>
-__device__ __forceinline__ Attempt group_attempt(const Params& P, GroupTraj<TB, F>& s, int c) {
+__device__ __forceinline__ Attempt group_attempt(const Params& P, const GroupCoef<TB>& cf,
+                                                 GroupTraj<TB, F>& s, int c) {
   constexpr int S = TB::S, D = F::D;
   const bool mine = c < D;
   Attempt a;
@@ -656,30 +736,24 @@ __device__ __forceinline__ Attempt group_attempt(const Params& P, GroupTraj<TB, 
     double acc = 0.0;
     sfor<j>([&](auto L) {
       constexpr int l = decltype(L)::value;
-      constexpr double aj = TB::A(j, l);
-      if constexpr (aj != 0.0) acc = fma(aj, s.k[l], acc);
+      if constexpr (TB::A(j, l) != 0.0) acc = fma(cf.a[j][l], s.k[l], acc);
     });
     const double Yc = fma(hh, acc, s.y);
-    double Y[D], kf[D];
-    row_gather<D>(Yc, Y);
-    F::f(s.t + TB::C(j) * hh, Y, s.in.par, kf);
-    s.k[j] = mine ? pick<D>(kf, c) : 0.0;
+    s.k[j] = RowRhs<F>::f(s.t + cf.template node<j>() * hh, Yc, s.in.par, c);
     if constexpr (TB::FSAL && j == S - 1) yn = Yc;
   });
   if constexpr (!TB::FSAL) {
     double acc = 0.0;
     sfor<S>([&](auto J) {
       constexpr int j = decltype(J)::value;
-      constexpr double b = TB::B(j);
-      if constexpr (b != 0.0) acc = fma(b, s.k[j], acc);
+      if constexpr (TB::B(j) != 0.0) acc = fma(cf.b[j], s.k[j], acc);
     });
     yn = fma(hh, acc, s.y);
   }
   double e = 0.0;
   sfor<S>([&](auto J) {
     constexpr int j = decltype(J)::value;
-    constexpr double w = TB::E(j);
-    if constexpr (w != 0.0) e = fma(w, s.k[j], e);
+    if constexpr (TB::E(j) != 0.0) e = fma(cf.e[j], s.k[j], e);
   });
   e *= hh;
   const double sc = fma(s.in.rtol, dmax(fabs(s.y), fabs(yn)), s.in.atol);
@@ -697,10 +771,7 @@ __device__ __forceinline__ Attempt group_attempt(const Params& P, GroupTraj<TB, 
   if constexpr (TB::FSAL) {
     s.k[0] = acc ? s.k[S - 1] : s.k[0];
   } else {
-    double Y[D], kf[D];
-    row_gather<D>(s.y, Y);
-    F::f(s.t, Y, s.in.par, kf);
-    s.k[0] = mine ? pick<D>(kf, c) : 0.0;
+    s.k[0] = RowRhs<F>::f(s.t, s.y, s.in.par, c);
   }
   s.err_prev2 = acc ? dmax(en2, 1e-8) : s.err_prev2;
   s.nacc += acc ? 1 : 0;
@@ -728,6 +799,8 @@ __device__ void solve_group(const Params& P) {
   const int c = lane & (kGroup - 1);
   const int first = lane & ~(kGroup - 1);  // the group's lane 0
   GroupTraj<TB, F> s;
+  GroupCoef<TB> cf;
+  cf.load();
   int64_t idx = -1;
   bool live = false;
   bool queue_empty = false;
@@ -801,7 +874,7 @@ __device__ void solve_group(const Params& P) {
         if ((int64_t)s.nacc + s.nrej >= P.max_steps) {
           st = ST_MAX_STEPS;
         } else {
-          const Attempt a = group_attempt<TB, F>(P, s, c);
+          const Attempt a = group_attempt<TB, F>(P, cf, s, c);
           if (a.finished) st = a.status;
         }
       }
