@@ -27,7 +27,7 @@ REFILLS = (1, 4, 8, 16, 64)
 # Trajectories at the head of the queue order run on 16-lane groups (wide):
 # tried on the best shapes when the call allows it (queue schedule, no
 # output nodes, no tape, at most 16 state components).
-WIDES = (1024, 2048, 4096, 8192)
+WIDES = (256, 512, 1024, 2048, 4096)
 CKPT = (1, 8, 32, 128)  # 1 = store mode: every accepted step on the tape
 
 

@@ -219,14 +219,17 @@ const Ops& ops(int rhs, int tab) {
 }
 
 // Grid of the forward launch: static mode covers n lanes; the persistent
-// queue mode fills every CU to its occupancy limit but never launches more
-// lanes than trajectories.
-void solve_shape(const gs_solve_args* a, int* grid, int* block) {
+// queue mode fills every CU to its occupancy limit (or takes the caller's
+// grid) but never launches more lanes than trajectories.  `limit` is the
+// grid before that last clip: the most workgroups the launch may hold.
+void solve_shape(const gs_solve_args* a, int* grid, int* block, int64_t* limit = nullptr) {
   const int b = a->block > 0 ? a->block : 256;
   const int64_t need = (a->n + b - 1) / b;
+  int64_t lim = need;
   if (a->schedule == GS_SCHED_STATIC) {
     *grid = (int)need;
   } else if (a->grid > 0) {
+    lim = a->grid;
     *grid = (int)std::min<int64_t>(a->grid, need);
   } else {
     int per_cu = 0;
@@ -235,9 +238,29 @@ void solve_shape(const gs_solve_args* a, int* grid, int* block) {
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, b, 0) != hipSuccess ||
         per_cu < 1)
       per_cu = 1;
-    *grid = (int)std::min<int64_t>((int64_t)per_cu * num_cus(), need);
+    lim = (int64_t)per_cu * num_cus();
+    *grid = (int)std::min<int64_t>(lim, need);
   }
   *block = b;
+  if (limit) *limit = lim;
+}
+
+// Split of a forward launch with `wide` trajectories on 16-lane groups.  The
+// group workgroups (block / 16 groups each) and the single-lane workgroups
+// draw from separate persistent queues.  Both together stay within `limit`
+// (a persistent grid must be resident as a whole): the single lanes keep
+// the workgroups they need, up to half of the limit, and the groups take
+// the rest, as many as start every wide trajectory at once if that fits.
+void wide_split(int64_t n, int64_t n_wide, int block, int64_t limit, int* wide_blocks,
+                int* grid) {
+  const int64_t per_block = block / gs::kGroup;
+  const int64_t want_w = (n_wide + per_block - 1) / per_block;
+  const int64_t need_s = (n - n_wide + block - 1) / block;
+  const int64_t keep_s = std::min<int64_t>(need_s, std::max<int64_t>(limit / 2, 1));
+  const int64_t w = std::min<int64_t>(want_w, std::max<int64_t>(limit - keep_s, 1));
+  const int64_t single = std::max<int64_t>(std::min<int64_t>(need_s, limit - w), 1);
+  *wide_blocks = (int)w;
+  *grid = (int)(w + single);
 }
 
 gs_status launch_solve_all(const gs_solve_args* a) {
@@ -246,18 +269,13 @@ gs_status launch_solve_all(const gs_solve_args* a) {
   Params P2 = P;
   hipLaunchKernelGGL(reset_queues_kernel, dim3(1), dim3(64), 0, s, P.counters, (long long)P.n_wide);
   int grid = 0, block = 0;
-  solve_shape(a, &grid, &block);
+  int64_t limit = 0;
+  solve_shape(a, &grid, &block, &limit);
   if (is_stiff(a)) {
     gs_host::launch_stiff(a->rhs, P, grid, block, s);
     return hipGetLastError() == hipSuccess ? GS_OK : GS_ERR_HIP;
   }
-  if (P.n_wide > 0) {
-    // One workgroup holds block / 16 groups; all wide trajectories start at
-    // once, ahead of the single-lane workgroups.
-    const int per_block = block / gs::kGroup;
-    P2.wide_blocks = (int)((P.n_wide + per_block - 1) / per_block);
-    grid = std::max(grid - P2.wide_blocks, 1) + P2.wide_blocks;
-  }
+  if (P.n_wide > 0) wide_split(P.n, P.n_wide, block, limit, &P2.wide_blocks, &grid);
   ops(a->rhs, a->tableau).solve(P2, grid, block, s);
   return hipGetLastError() == hipSuccess ? GS_OK : GS_ERR_HIP;
 }

@@ -268,7 +268,11 @@ __device__ __forceinline__ double ipow(double r) {
 
 // x^(-1/M) for x in [1e-30, 1e30]: an FP32 seed from the hardware log2/exp2,
 // then two Newton steps on r^M x = 1 in FP64 (relative error ~(M+1)/2 eps^2
-// per step, so full double precision after two).
+// per step, so full double precision after two).  A single third-order
+// correction reaches the same error bound with fewer dependent operations,
+// but lands on a different last bit than the oracle's pow more often; the
+// step sizes then drift apart at the rounding level and the 900-step
+// precession solves leave the 1e-9 parity bar, so the Newton steps stay.
 template <int M>
 __device__ __forceinline__ double inv_root(double x) {
   const float lx = __builtin_amdgcn_logf(static_cast<float>(x));
@@ -574,12 +578,13 @@ struct FwdOccupancy {
 // Group mode: one trajectory on a group of 16 lanes (a DPP row), lane c of
 // the group holding component c of the state and of every stage.  Stage
 // sums and error terms are the single-lane expressions for that component;
-// each stage point is broadcast within the row so that every lane evaluates
-// the ordinary right-hand side on the full vector and keeps its component;
-// the norm is a butterfly over the row whose pairing is the pairwise order
-// of error_norm2 (lanes beyond d hold +0, which adds exactly).  A group
-// therefore takes the same steps, bit for bit, as a single lane, with about
-// a sixth of the stage arithmetic on the critical path of one trajectory.
+// the right-hand side is evaluated per component where one is written for
+// the row (RowRhs), else each stage point is broadcast within the row so
+// that every lane evaluates the ordinary right-hand side on the full vector
+// and keeps its component; the norm sums the broadcast terms of lanes
+// 0..d-1 in the pairwise order of error_norm2.  A group therefore takes the
+// same steps, bit for bit, as a single lane, with about a sixth of the stage
+// arithmetic on the critical path of one trajectory.
 constexpr int kGroup = 16;
 
 // A DPP move of a double within each row of 16 lanes.  Lanes whose source
@@ -599,15 +604,22 @@ __device__ __forceinline__ double row_bcast(double v) {
   return __longlong_as_double(
       __builtin_amdgcn_mov_dpp(__double_as_longlong(v), 0x150 + SRC, 0xF, 0xF, true));
 }
-// Sum over the 16 lanes of the row: partners l^1, l^2 (quad_perm), then the
-// other quad of the half-row (row_half_mirror), then the other half-row
-// (row_mirror); every lane ends with the same value.
+// Sum of lanes 0..D-1 of the row, in every lane of the row: each value is
+// broadcast and the sum taken in the pairwise order of error_norm2 (pairs,
+// then pairs of pairs, ...), so a group's norm has the bits of one lane's.
+template <int D>
 __device__ __forceinline__ double row_sum(double v) {
-  v = v + dpp_mov<0xB1>(v);
-  v = v + dpp_mov<0x4E>(v);
-  v = v + dpp_mov<0x141>(v);
-  v = v + dpp_mov<0x140>(v);
-  return v;
+  double q[D];
+  sfor<D>([&](auto C) {
+    constexpr int c = decltype(C)::value;
+    q[c] = row_bcast<c>(v);
+  });
+#pragma unroll
+  for (int w = 1; w < D; w *= 2) {
+#pragma unroll
+    for (int c = 0; c + w < D; c += 2 * w) q[c] += q[c + w];
+  }
+  return q[0];
 }
 
 // Full vector of the row's components (lanes 0..D-1), in every lane.
@@ -720,7 +732,6 @@ template <class TB, class F>
 __device__ __forceinline__ Attempt group_attempt(const Params& P, const GroupCoef<TB>& cf,
                                                  GroupTraj<TB, F>& s, int c) {
   constexpr int S = TB::S, D = F::D;
-  const bool mine = c < D;
   Attempt a;
   a.t_start = s.t;
   bool last = false;
@@ -758,14 +769,14 @@ __device__ __forceinline__ Attempt group_attempt(const Params& P, const GroupCoe
   e *= hh;
   const double sc = fma(s.in.rtol, dmax(fabs(s.y), fabs(yn)), s.in.atol);
   const double r = e * fast_rcp1(sc);
-  const double en2 = row_sum(mine ? r * r : 0.0) * (1.0 / D);
+  const double en2 = row_sum<D>(r * r) * (1.0 / D);
   const bool finite = (en2 - en2) == 0.0;
   const double factor = step_factor<TB>(P, en2, s.err_prev2, finite);
   const bool acc = finite & (en2 <= 1.0);
   a.accepted = acc;
   const double t_new = last ? s.in.t1 : s.t + hh;
   a.t_new = t_new;
-  const bool fin = row_sum(mine ? fma(yn, 0.0, 0.0) : 0.0) == 0.0;
+  const bool fin = row_sum<D>(fma(yn, 0.0, 0.0)) == 0.0;
   s.y = acc ? yn : s.y;
   s.t = acc ? t_new : s.t;
   if constexpr (TB::FSAL) {
@@ -798,6 +809,11 @@ __device__ void solve_group(const Params& P) {
   const int lane = threadIdx.x & 63;
   const int c = lane & (kGroup - 1);
   const int first = lane & ~(kGroup - 1);  // the group's lane 0
+  // The groups carry the longest trajectories and issue an instruction only
+  // every few cycles (each waits on the one before); the highest wave
+  // priority lets them issue first on a SIMD they share with single-lane
+  // waves, which fill the idle cycles in between.
+  __builtin_amdgcn_s_setprio(3);
   GroupTraj<TB, F> s;
   GroupCoef<TB> cf;
   cf.load();

@@ -103,11 +103,24 @@ def orbits_uneven(n=100_000, seed=2):
 
 
 def predicted_cost(w):
-    """Heuristic cost of each trajectory for longest-first queue order:
-    span times rtol^(-1/5) (a 5th-order method's steps per unit time)."""
-    span = np.broadcast_to(np.asarray(w["t1"], float) - np.asarray(w["t0"], float),
-                           (w["y0"].shape[1],))
+    """Heuristic cost of each trajectory for longest-first queue order: the
+    number of dynamical times in the span times rtol^(-1/5) (a 5th-order
+    method's steps per dynamical time).  For orbits in the logarithmic halo
+    the dynamical time is (rc + r_E) / v0, with r_E the radius in the plane
+    at which the potential equals the orbit's energy; otherwise the span
+    itself stands in for it."""
+    n = w["y0"].shape[1]
+    span = np.broadcast_to(np.asarray(w["t1"], float) - np.asarray(w["t0"], float), (n,))
     rtol = np.broadcast_to(np.asarray(w["rtol"], float), span.shape)
+    if w["rhs"] == "loghalo":
+        th = np.asarray(w["theta"], float)
+        th = th[:, None] if th.ndim == 1 else th
+        v0, q, rc = (np.broadcast_to(th[i], (n,)) for i in range(3))
+        y = w["y0"]
+        Dn = rc * rc + y[0] ** 2 + y[1] ** 2 + y[2] ** 2 / (q * q)
+        E = 0.5 * (y[3] ** 2 + y[4] ** 2 + y[5] ** 2) + 0.5 * v0 * v0 * np.log(Dn)
+        r_E = np.sqrt(np.maximum(np.exp(2.0 * E / (v0 * v0)) - rc * rc, 0.0))
+        span = span * v0 / (rc + r_E)
     return span * rtol ** (-0.2)
 
 
