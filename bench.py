@@ -500,8 +500,10 @@ def main():
         "data": "synthetic",
         "config": {"workload": "orbits_uneven_100k", "n": n, "rhs": "loghalo",
                    "tableau": "tsit5", "rtol": "logU[1e-9,1e-6]", "t_end": "logU[10,500]",
-                   "launch": "persistent queue, longest-first, hipGraph, autotuned",
-                   "block": launch.block, "grid": launch.grid, "refill": launch.refill},
+                   "launch": "persistent queue, longest-first by predicted dynamical times, "
+                             "head of the order on 16-lane groups, hipGraph, autotuned",
+                   "block": launch.block, "grid": launch.grid, "refill": launch.refill,
+                   "wide": launch.wide},
         "accepted_steps_per_s": nacc / (ms * 1e-3),
         "attempts_per_s": attempts / (ms * 1e-3),
         "all_trajectories_ok": ok,
