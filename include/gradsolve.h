@@ -169,7 +169,12 @@ typedef struct gs_solve_args {
                             lane) in the same launch, for the long tail of
                             uneven ensembles; results are bit-identical to
                             one lane per trajectory.  0 = none.  Needs the
-                            queue schedule, K = 0 and no tape.              */
+                            queue schedule, K = 0 and no tape.  The groups
+                            refill from their own queue; they and the single
+                            lanes share the grid (the occupancy limit, or
+                            `grid` when given), the single lanes keeping up
+                            to half of it, each side at least one
+                            workgroup.                                      */
   const int64_t* order;  /* [n] queue order (a permutation of 0..n-1), or
                             NULL for 0, 1, ..., n-1                         */
 

@@ -248,7 +248,8 @@ void solve_shape(const gs_solve_args* a, int* grid, int* block, int64_t* limit =
 // Split of a forward launch with `wide` trajectories on 16-lane groups.  The
 // group workgroups (block / 16 groups each) and the single-lane workgroups
 // draw from separate persistent queues.  Both together stay within `limit`
-// (a persistent grid must be resident as a whole): the single lanes keep
+// (a persistent grid must be resident as a whole), except that each side
+// that has trajectories gets at least one workgroup: the single lanes keep
 // the workgroups they need, up to half of the limit, and the groups take
 // the rest, as many as start every wide trajectory at once if that fits.
 void wide_split(int64_t n, int64_t n_wide, int block, int64_t limit, int* wide_blocks,
@@ -258,7 +259,8 @@ void wide_split(int64_t n, int64_t n_wide, int block, int64_t limit, int* wide_b
   const int64_t need_s = (n - n_wide + block - 1) / block;
   const int64_t keep_s = std::min<int64_t>(need_s, std::max<int64_t>(limit / 2, 1));
   const int64_t w = std::min<int64_t>(want_w, std::max<int64_t>(limit - keep_s, 1));
-  const int64_t single = std::max<int64_t>(std::min<int64_t>(need_s, limit - w), 1);
+  const int64_t single =
+      need_s > 0 ? std::max<int64_t>(std::min<int64_t>(need_s, limit - w), 1) : 0;
   *wide_blocks = (int)w;
   *grid = (int)(w + single);
 }

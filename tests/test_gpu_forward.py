@@ -208,3 +208,18 @@ def test_wide_groups_on_the_uneven_batch(orc):
         np.testing.assert_array_equal(g[k], ref[k])
     idx = np.sort(np.concatenate([order[:60], order[-40:]]))
     _check(g, oracle_solve(orc, w, idx), idx)
+
+
+@pytest.mark.parametrize("grid,wide", [(3, 500), (2, 2000), (6, 40)], ids=["g3w500", "g2wall", "g6w40"])
+def test_wide_groups_with_a_small_grid(grid, wide):
+    """More wide trajectories than groups the grid holds: the groups refill
+    from their own queue, at least one workgroup keeps the single lanes, and
+    the results are bitwise those of one lane per trajectory."""
+    w = inputs.orbits_uneven(n=2000, seed=48)
+    w = {**w, "t1": np.minimum(w["t1"], 40.0)}
+    order = np.argsort(-inputs.predicted_cost(w), kind="stable")
+    ref = to_np(gpu_solve(w, order=order))
+    g = to_np(gpu_solve(w, api.Launch(block=64, grid=grid, wide=wide), order=order))
+    assert np.all(ref["status"] == 0)
+    for k in ref:
+        np.testing.assert_array_equal(g[k], ref[k], err_msg=k)
