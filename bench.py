@@ -472,12 +472,17 @@ def main():
     tw = inputs.orbits_uneven(n=nt, seed=6)
     tprob = api.make_problem(tw["rhs"], "tsit5", tw["y0"], tw["theta"], 0.0, np.full(nt, 20.0),
                              np.full(nt, 1e-8), np.full(nt, 1e-8))
-    tsol = api.Solution(tprob, autotune.tune_forward(tprob, use_cache=False))
+    tw.update(t0=0.0, t1=np.full(nt, 20.0), rtol=np.full(nt, 1e-8), atol=np.full(nt, 1e-8))
+    torder = np.argsort(-inputs.predicted_cost(tw), kind="stable")
+    tsol = api.Solution(tprob, autotune.tune_forward(tprob, order=torder, use_cache=False))
+    tsol.set_order(torder)
     ms_t = timed(lambda: tsol.run(), 3, 1, torch)
     att_t = int((tsol.n_accepted + tsol.n_rejected).to(torch.int64).sum())
     ach_t = att_t * fpa / (ms_t * 1e-3) / 1e12
-    throughput = {"workload": "1,000,000 orbits, t = 20, rtol = atol = 1e-8, Tsit5",
-                  "launch": {k: tsol.launch.__dict__[k] for k in ("block", "grid", "refill")},
+    throughput = {"workload": "1,000,000 orbits, t = 20, rtol = atol = 1e-8, Tsit5, "
+                              "longest-first by predicted dynamical times",
+                  "launch": {k: tsol.launch.__dict__[k] for k in ("block", "grid", "refill",
+                                                                   "wide")},
                   "ms": round(ms_t, 3), "attempts": att_t, "achieved": round(ach_t, 3),
                   "unit": "TFLOP/s", "frac": round(ach_t / PEAK_FP64_VECTOR_TFLOPS, 4)}
     log(f"[bench] kernel {ms_kernel:.3f} ms = {achieved:.2f} TFLOP/s; lone wave "
