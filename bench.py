@@ -57,6 +57,11 @@ PEAK_FP64_VECTOR_TFLOPS = 78.6   # MI355X: 256 CU x 2.4 GHz x 128 FP64 flop/clk
 FLOPS_PER_ATTEMPT = {("tsit5", "loghalo"): 541, ("dopri5", "loghalo"): 517,
                      ("verner7", "spinprec"): 2367}
 FLOPS_PER_NODE = {("verner7", "spinprec"): 2025}
+# Reverse of one accepted step (store-mode tape, one loss): recompute the first
+# right-hand side, the stage points and right-hand sides of the stages that feed
+# the step, then seed h b_j lam, reverse every feeding stage through the
+# right-hand side's VJP (46 flops for the log halo) and the transposed stage sums.
+FLOPS_PER_VJP_STEP = {("dopri5", "loghalo"): 880}
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles",
                                "traffic_solve_kernel_tsit5_loghalo_orbits_uneven_100k.md")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2609_28458_amd", "csrc", f)
@@ -588,7 +593,63 @@ def main():
         same = all(torch.equal(a, b) for a, b in zip(grads[0], grads[(pg.n + 255) // 256]))
         log(f"[bench] gradient arms: fused persistent {ms_fused:.3f} ms, one lane per trajectory "
             f"{ms_stat:.3f} ms, identical gradients {same}")
+        # The adjoint kernel alone (store-mode tape, HIP events on its stream): algorithmic
+        # flops are the per-accepted-step count of the reverse step times the accepted steps.
+        fused.run()
+        ybf[0, :3] = 2.0 * (fused.y_final[:3] - T)
+        steps_g = int(fused.n_accepted.to(torch.int64).sum())
+        ms_vjp = timed(lambda: api.solve_vjp(fused, ybar_final=ybf), max(3, args.steps // 4), 1,
+                       torch)
+        fvs = FLOPS_PER_VJP_STEP[("dopri5", "loghalo")]
+        ach_vjp = steps_g * fvs / (ms_vjp * 1e-3) / 1e12
+        vjp_roofline = {"kernel": "gs::vjp_kernel<Dopri5, LogHalo>, store-mode tape",
+                        "bound": "alu", "flops_per_accepted_step": fvs,
+                        "accepted_steps": steps_g, "ms": round(ms_vjp, 4),
+                        "achieved": round(ach_vjp, 3), "peak": PEAK_FP64_VECTOR_TFLOPS,
+                        "unit": "TFLOP/s", "frac": round(ach_vjp / PEAK_FP64_VECTOR_TFLOPS, 4)}
+        # Its critical path: the longest orbit of the workload alone (forward with tape,
+        # then the adjoint).
+        i_g = int(torch.argmax(fused.n_accepted))
+        one_g = {k: (v[..., [i_g]] if isinstance(v, np.ndarray) and v.shape[-1:] == (pg.n,)
+                     else v) for k, v in wg.items()}
+        p1 = api.make_problem(one_g["rhs"], one_g["tableau"], one_g["y0"], one_g["theta"],
+                              one_g["t0"], one_g["t1"], one_g["rtol"], one_g["atol"])
+        s1 = api.Solution(p1, api.Launch(block=64, ckpt_every=1, ckpt_capacity=cap1))
+        ms_f1 = timed(lambda: s1.run(), 3, 1, torch)
+        yb1 = torch.ones((1, 6, 1), dtype=torch.float64, device="cuda")
+        ms_v1 = timed(lambda: api.solve_vjp(s1, ybar_final=yb1), 3, 1, torch)
+        vjp_roofline["critical_path"] = {
+            "max_accepted_one_orbit": int(fused.n_accepted.max()),
+            "longest_alone_ms": {"forward_with_tape": round(ms_f1, 3), "adjoint": round(ms_v1, 3)},
+            "batch_adjoint_over_longest_alone": round(ms_vjp / ms_v1, 3)}
+        log(f"[bench] adjoint kernel alone: {ms_vjp:.3f} ms, {ach_vjp:.2f} TFLOP/s "
+            f"({100 * ach_vjp / PEAK_FP64_VECTOR_TFLOPS:.1f}% of FP64 peak); longest orbit alone "
+            f"{ms_v1:.3f} ms")
+        # The adjoint with the chip full: 10^6 orbits (t = 20, Dopri5 1e-8), store-mode tape.
+        nv = 1_000_000
+        vw = inputs.orbits_uneven(n=nv, seed=6)
+        vp = api.make_problem(vw["rhs"], "dopri5", vw["y0"], vw["theta"], 0.0, np.full(nv, 20.0),
+                              np.full(nv, 1e-8), np.full(nv, 1e-8))
+        vplain = api.solve(vp, api.Launch(block=128))
+        torch.cuda.synchronize()
+        vcap = int(vplain.n_accepted.max()) + 2
+        del vplain
+        vsol = api.Solution(vp, api.Launch(block=128, ckpt_every=1, ckpt_capacity=vcap))
+        vsol.run()
+        vyb = vsol.y_final.clone().unsqueeze(0)
+        vsteps = int(vsol.n_accepted.to(torch.int64).sum())
+        ms_vf = timed(lambda: api.solve_vjp(vsol, ybar_final=vyb), 3, 1, torch)
+        ach_vf = vsteps * fvs / (ms_vf * 1e-3) / 1e12
+        vjp_roofline["full_chip"] = {
+            "workload": "1,000,000 orbits, t = 20, Dopri5 rtol = atol = 1e-8, store-mode tape",
+            "accepted_steps": vsteps, "ms": round(ms_vf, 4), "achieved": round(ach_vf, 3),
+            "frac": round(ach_vf / PEAK_FP64_VECTOR_TFLOPS, 4)}
+        log(f"[bench] adjoint kernel, chip full: {ms_vf:.3f} ms, {ach_vf:.2f} TFLOP/s "
+            f"({100 * ach_vf / PEAK_FP64_VECTOR_TFLOPS:.1f}%)")
+        del vsol, vyb
+        torch.cuda.empty_cache()
         out["grad"] = {"workload": "orbits_gradient_100k", "ms_forward": round(ms_fwd, 4),
+                       "vjp_roofline": vjp_roofline,
                        "ms_forward_tape_plus_vjp": round(best[1], 4), "ckpt_every": best[0],
                        "ms_by_ckpt_every": per_k,
                        "arms_ms": {"fused_persistent_store_tape": round(ms_fused, 4),

@@ -176,7 +176,8 @@ typedef struct gs_solve_args {
                             to half of it, each side at least one
                             workgroup.                                      */
   const int64_t* order;  /* [n] queue order (a permutation of 0..n-1), or
-                            NULL for 0, 1, ..., n-1                         */
+                            NULL for 0, 1, ..., n-1; gs_solve_vjp takes the
+                            trajectories in the same order                  */
 
   void* workspace;       /* device memory, >= gs_workspace_bytes(args),
                             256-byte aligned.  Bytes 16..23 hold a uint64

@@ -809,11 +809,6 @@ __device__ void solve_group(const Params& P) {
   const int lane = threadIdx.x & 63;
   const int c = lane & (kGroup - 1);
   const int first = lane & ~(kGroup - 1);  // the group's lane 0
-  // The groups carry the longest trajectories and issue an instruction only
-  // every few cycles (each waits on the one before); the highest wave
-  // priority lets them issue first on a SIMD they share with single-lane
-  // waves, which fill the idle cycles in between.
-  __builtin_amdgcn_s_setprio(3);
   GroupTraj<TB, F> s;
   GroupCoef<TB> cf;
   cf.load();
@@ -1366,7 +1361,10 @@ __global__ void __launch_bounds__(256) vjp_kernel(Params P, VjpParams V) {
         if (base + (unsigned long long)nidle >= (unsigned long long)P.n) queue_empty = true;
         if (!live) {
           const unsigned long long pos = base + __popcll(idle & lanemask_lt());
-          if (pos < (unsigned long long)P.n) start((int64_t)pos);
+          if (pos < (unsigned long long)P.n) {
+            const int64_t id = P.order ? P.order[pos] : (int64_t)pos;
+            if (id >= 0 && id < P.n) start(id);  // a bad permutation entry is skipped
+          }
         }
       }
     }

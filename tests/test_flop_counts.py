@@ -37,3 +37,29 @@ def test_flops_per_attempt_follow_the_tableaux(orc):
 def test_stiff_flops_formula():
     assert bench.rodas4_flops_per_attempt(8, 6, 28) == 1918
     assert bench.rodas4_flops_per_attempt(3, 3, 7) == 419
+
+
+V_F = {"loghalo": 46}  # the log halo's VJP as the kernels evaluate it
+
+
+def test_flops_per_vjp_step_follow_the_tableau(orc):
+    """Reverse of one accepted step: the first right-hand side; for every
+    stage j >= 1 that feeds the step (b_j != 0 or a later a_ij != 0) its
+    stage sum 2 d (nnz(row j) + 1), stage time 2 and, unless it is the last
+    stage, its right-hand side; the seeds h b_j lam (1 + d per nonzero b_j);
+    then for every feeding stage the VJP, the d-term accumulation into y,
+    the stage time for j >= 1, and (1 + 2 d) per nonzero a_jl of its row."""
+    for (tab, rhs), flops in bench.FLOPS_PER_VJP_STEP.items():
+        t = orc.tableau(tab)
+        s, d, a, b = t["s"], DIM[rhs], np.asarray(t["a"]), np.asarray(t["b"])
+        feeds = [b[j] != 0 or np.any(a[j + 1:, j] != 0) for j in range(s)]
+        nnz_row = [int(np.count_nonzero(a[j, :j])) for j in range(s)]
+        total = F_F[rhs]
+        for j in range(1, s):
+            if feeds[j]:
+                total += 2 * d * (nnz_row[j] + 1) + 2 + (F_F[rhs] if j < s - 1 else 0)
+        total += int(np.count_nonzero(b)) * (1 + d)
+        for j in range(s):
+            if feeds[j]:
+                total += V_F[rhs] + d + (2 if j >= 1 else 0) + nnz_row[j] * (1 + 2 * d)
+        assert total == flops, (tab, rhs, total)
