@@ -80,12 +80,21 @@ def test_every_rhs_and_tableau(orc, name, make, tab):
 
 def test_uneven_batch_full_size_sampled(orc):
     """The full 100,000-orbit uneven batch on the GPU (persistent queue,
-    longest-first order); 1,500 sampled orbits recomputed by the oracle."""
+    longest-first order), in the benchmark's launch shapes with the head of
+    the order on 16-lane groups: bitwise equal to one lane per trajectory,
+    and 1,500 sampled orbits plus the 60 predicted-longest (on groups)
+    recomputed by the oracle."""
     w = inputs.orbits_uneven()
     order = np.argsort(-inputs.predicted_cost(w), kind="stable")
     g = to_np(gpu_solve(w, order=order))
     assert np.all(g["status"] == 0)
-    idx = np.sort(np.random.default_rng(7).choice(w["y0"].shape[1], 1500, replace=False))
+    for L in (api.Launch(block=128, refill=8, wide=256),
+              api.Launch(block=256, refill=4, wide=512)):
+        gw = to_np(gpu_solve(w, L, order=order))
+        for k in g:
+            np.testing.assert_array_equal(gw[k], g[k], err_msg=f"{k} {L}")
+    rnd = np.random.default_rng(7).choice(w["y0"].shape[1], 1500, replace=False)
+    idx = np.unique(np.concatenate([rnd, order[:60]]))
     o = oracle_solve(orc, w, idx)
     _check(g, o, idx)
 
