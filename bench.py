@@ -56,7 +56,7 @@ PEAK_FP64_VECTOR_TFLOPS = 78.6   # MI355X: 256 CU x 2.4 GHz x 128 FP64 flop/clk
 #   9 evaluations and the stage sums and update, 1071 + 810 + 144 = 2025.
 FLOPS_PER_ATTEMPT = {("tsit5", "loghalo"): 541, ("dopri5", "loghalo"): 517,
                      ("verner7", "spinprec"): 2367}
-FLOPS_PER_NODE = {("verner7", "spinprec"): 2025}
+FLOPS_PER_NODE = {("verner7", "spinprec"): 2025, ("dopri5", "loghalo"): 168}
 # Reverse of one accepted step (store-mode tape, one loss): recompute the first
 # right-hand side, the stage points and right-hand sides of the stages that feed
 # the step, then seed h b_j lam, reverse every feeding stage through the
@@ -490,6 +490,34 @@ def main():
                                                                    "wide")},
                   "ms": round(ms_t, 3), "attempts": att_t, "achieved": round(ach_t, 3),
                   "unit": "TFLOP/s", "frac": round(ach_t / PEAK_FP64_VECTOR_TFLOPS, 4)}
+    # The 1,000-orbit forward recipe (shared halo, Dopri5 1e-8/1e-10, 64 outputs to t = 50)
+    # at 10^6 orbits: its roofline with the chip full, outputs included.
+    nc = 1_000_000
+    cw = inputs.orbits_forward(n=nc, seed=1)
+    cprob = api.make_problem(cw["rhs"], cw["tableau"], cw["y0"], cw["theta"], cw["t0"],
+                             cw["t1"], cw["rtol"], cw["atol"], cw["t_out"])
+    corder = np.argsort(-inputs.predicted_cost(cw), kind="stable")
+    csol = api.Solution(cprob, autotune.tune_forward(cprob, order=corder, use_cache=False))
+    csol.set_order(corder)
+    ms_c = timed(lambda: csol.run(), 3, 1, torch)
+    att_c = int((csol.n_accepted + csol.n_rejected).to(torch.int64).sum())
+    fl_c = (att_c * FLOPS_PER_ATTEMPT[("dopri5", "loghalo")]
+            + nc * cprob.K * FLOPS_PER_NODE[("dopri5", "loghalo")])
+    ach_c = fl_c / (ms_c * 1e-3) / 1e12
+    c1_million = {"workload": "1,000,000 orbits of the 1,000-orbit forward recipe: shared halo, "
+                              "Dopri5 1e-8/1e-10, 64 outputs to t = 50, longest-first",
+                  "launch": {k: csol.launch.__dict__[k] for k in ("block", "grid", "refill")},
+                  "ms": round(ms_c, 3), "attempts": att_c,
+                  "flops_per_attempt": FLOPS_PER_ATTEMPT[("dopri5", "loghalo")],
+                  "flops_per_output": FLOPS_PER_NODE[("dopri5", "loghalo")],
+                  "output_gb_per_s": round(6 * cprob.K * nc * 8 / (ms_c * 1e-3) / 1e9, 1),
+                  "achieved": round(ach_c, 3), "unit": "TFLOP/s",
+                  "frac": round(ach_c / PEAK_FP64_VECTOR_TFLOPS, 4),
+                  "all_ok": bool((csol.status == 0).all())}
+    log(f"[bench] 10^6 orbits, 64 outputs: {ms_c:.3f} ms, {ach_c:.2f} TFLOP/s "
+        f"({100 * ach_c / PEAK_FP64_VECTOR_TFLOPS:.1f}%)")
+    del csol
+    torch.cuda.empty_cache()
     log(f"[bench] kernel {ms_kernel:.3f} ms = {achieved:.2f} TFLOP/s; lone wave "
         f"{us_per_attempt:.3f} us/attempt, lone group {us_group:.3f} us/attempt -> longest "
         f"orbit alone {bound_ms:.2f} ms; full chip "
@@ -520,6 +548,7 @@ def main():
         "device": dev_name,
         "roofline": roofline,
         "roofline_full_chip": throughput,
+        "roofline_c1_million": c1_million,
     }
 
     # ---- the other two arms of the same batch -------------------------------------------

@@ -2,7 +2,8 @@
 FLOPS_PER_ATTEMPT / FLOPS_PER_NODE) against the same formula evaluated on the
 oracle's own tableaux: stage sums 2 d (nnz(A) + s - 1), the update of a
 non-FSAL pair 2 d (nnz(b) + 1), stage times 2 (s - 1), error weights
-2 d nnz(b - bhat) + d, norm 5 d + 2, controller 5, and F_f per new stage.
+2 d nnz(b - bhat) + d, norm 5 d + 2, controller 5, and F_f per new stage;
+per output node a polynomial evaluation or a shortened step.
 F_f is the hand count of each right-hand side as the kernels evaluate it
 (13 for the log halo, 119 for precession)."""
 import numpy as np
@@ -23,7 +24,13 @@ def _parts(orc, tab, rhs):
     s_new = s - 1 if t["fsal"] else s
     attempt = (2 * d * (nnz_a + s - 1) + update + 2 * (s - 1) + 2 * d * nnz_e + d
                + 5 * d + 2 + 5 + s_new * F_F[rhs])
-    node = (s - 1) * F_F[rhs] + 2 * d * (nnz_a + s - 1) + update
+    if t["deg"] > 0:
+        # polynomial output: the weights b_j(sigma) by Horner (2 deg + 2 each),
+        # d sums of s terms and the final fma, and sigma itself
+        node = s * (2 * t["deg"] + 2) + d * (2 * s + 2) + 2
+    else:
+        # a shortened step from the start of the step
+        node = (s - 1) * F_F[rhs] + 2 * d * (nnz_a + s - 1) + update
     return attempt, node
 
 
