@@ -1279,6 +1279,29 @@ __device__ __forceinline__ void reverse_step(const Inputs<F>& in, double t, doub
 // STORE: the tape is in store mode (chosen by the host from ckpt_every), so
 // the kernel holds no replay state at all.
 constexpr int kStoreSegment = 32;
+
+// A store-mode tape record (L consecutive doubles) held in registers as
+// 16-byte vectors, so that a fetch lands in the variable itself and nothing
+// copies it (a copy right after the fetch would wait for it); a record of
+// odd length keeps its last value alone, so nothing past the record is read.
+// The vectors claim only the 8-byte alignment a record has.
+template <int L>
+struct RecBuf {
+  typedef double d2 __attribute__((ext_vector_type(2), aligned(8)));
+  d2 v[L / 2];
+  double tail;
+  __device__ __forceinline__ void load(const double* p) {
+#pragma unroll
+    for (int k = 0; k < L / 2; ++k) v[k] = *reinterpret_cast<const d2*>(p + 2 * k);
+    if constexpr (L % 2 != 0) tail = p[L - 1];
+  }
+  __device__ __forceinline__ double get(int i) const {
+    if constexpr (L % 2 != 0) {
+      if (i == L - 1) return tail;
+    }
+    return v[i / 2][i % 2];
+  }
+};
 template <class TB, class F, int R, bool NODES, bool STORE>
 __global__ void __launch_bounds__(256) vjp_kernel(Params P, VjpParams V) {
   constexpr int D = F::D, NP = F::P;
@@ -1432,7 +1455,27 @@ __global__ void __launch_bounds__(256) vjp_kernel(Params P, VjpParams V) {
     };
     double nx_t = 0.0, nx_h = 0.0, nx_y[D];
     double h_carry = 0.0;  // store mode: h of the step about to be reversed
-    bool have = false;
+#pragma unroll
+    for (int c = 0; c < D; ++c) nx_y[c] = 0.0;
+    // The lane's first step of the segment (jj = m - 1) is read here, ahead
+    // of the loop, so that the loop body has one path: each step takes the
+    // record fetched one step earlier and issues the fetch of the next one,
+    // which then stays in flight during the step's arithmetic (a first-step
+    // branch inside the loop made the compiler wait for every outstanding
+    // load, the new fetch included, at the top of each step).
+    RecBuf<SREC> nxr;  // store mode: the record of the next step to reverse
+    if (live && ok && m > 0) {
+      const double* rec = record(m - 1);
+      if constexpr (store) {
+        nxr.load(rec);
+        h_carry = tape_record<TB, F>(P, idx, cseg * kseg + m)[1];
+      } else {
+        nx_t = rec[0];
+        nx_h = rec[fs];
+#pragma unroll
+        for (int c = 0; c < D; ++c) nx_y[c] = rec[(2 + c) * fs];
+      }
+    }
     // This segment's running cotangents (every lane reads its own slot, so
     // they are defined on every path).
     double lam[R][D], thb[R][NP];
@@ -1443,32 +1486,40 @@ __global__ void __launch_bounds__(256) vjp_kernel(Params P, VjpParams V) {
 #pragma unroll
       for (int c = 0; c < NP; ++c) thb[r][c] = THB(r, c);
     }
+    // Take these loads to completion here: left outstanding into the loop,
+    // the waits for them stay in the loop body and, memory counters being
+    // in order, make every later step wait for its own prefetch as well.
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+#pragma unroll
+      for (int c = 0; c < D; ++c) asm volatile("" : : "v"(lam[r][c]));
+#pragma unroll
+      for (int c = 0; c < NP; ++c) asm volatile("" : : "v"(thb[r][c]));
+    }
     for (int jj = kseg - 1; jj >= 0; --jj) {
       const bool act = live && ok && jj < m;
       if (__ballot(act) == 0) continue;
       if (!act) continue;
-      if (!have) {
-        // First step of the segment on this lane.
-        const double* rec = record(jj);
-        nx_t = rec[0];
-        nx_h = rec[fs];
+      double tn, hn, yn[D];
+      if constexpr (store) {
+        tn = nxr.get(0);
+        hn = h_carry;
 #pragma unroll
-        for (int c = 0; c < D; ++c) nx_y[c] = rec[(2 + c) * fs];
-        if constexpr (store) h_carry = tape_record<TB, F>(P, idx, cseg * kseg + jj + 1)[1];
-        have = true;
-      }
-      const double tn = nx_t;
-      const double hn = store ? h_carry : nx_h;
-      double yn[D];
+        for (int c = 0; c < D; ++c) yn[c] = nxr.get(2 + c);
+        h_carry = nxr.get(1);
+        if (jj > 0) nxr.load(record(jj - 1));
+      } else {
+        tn = nx_t;
+        hn = nx_h;
 #pragma unroll
-      for (int c = 0; c < D; ++c) yn[c] = nx_y[c];
-      if constexpr (store) h_carry = nx_h;
-      if (jj > 0) {
-        const double* rec = record(jj - 1);
-        nx_t = rec[0];
-        nx_h = rec[fs];
+        for (int c = 0; c < D; ++c) yn[c] = nx_y[c];
+        if (jj > 0) {
+          const double* rec = record(jj - 1);
+          nx_t = rec[0];
+          nx_h = rec[fs];
 #pragma unroll
-        for (int c = 0; c < D; ++c) nx_y[c] = rec[(2 + c) * fs];
+          for (int c = 0; c < D; ++c) nx_y[c] = rec[(2 + c) * fs];
+        }
       }
       const bool last_step = cseg * kseg + jj == N - 1;
       const double t_new = last_step ? s.in.t1 : tn + hn;
