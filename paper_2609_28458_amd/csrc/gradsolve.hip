@@ -234,7 +234,8 @@ void solve_shape(const gs_solve_args* a, int* grid, int* block, int64_t* limit =
   } else {
     int per_cu = 0;
     const void* fn =
-        is_stiff(a) ? gs_host::stiff_solve_fn(a->rhs) : ops(a->rhs, a->tableau).solve_fn;
+        is_stiff(a) ? gs_host::stiff_solve_fn(a->rhs)
+                    : ops(a->rhs, a->tableau).solve_fn[a->K > 0][a->ckpt_every > 0];
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, b, 0) != hipSuccess ||
         per_cu < 1)
       per_cu = 1;

@@ -88,7 +88,10 @@ void launch_sens(const gs::Params& P, const gs::SensParams& S, int M, int grid, 
 
 template <class TB, class F>
 Ops make_ops() {
-  return Ops{reinterpret_cast<const void*>(&gs::solve_kernel<TB, F, true, true>),
+  return Ops{{{reinterpret_cast<const void*>(&gs::solve_kernel<TB, F, false, false>),
+               reinterpret_cast<const void*>(&gs::solve_kernel<TB, F, false, true>)},
+              {reinterpret_cast<const void*>(&gs::solve_kernel<TB, F, true, false>),
+               reinterpret_cast<const void*>(&gs::solve_kernel<TB, F, true, true>)}},
              &launch_solve<TB, F>, &launch_vjp<TB, F>, &launch_dense<TB, F>, &launch_sens<TB, F>};
 }
 

@@ -11,7 +11,9 @@
 namespace gs_host {
 
 struct Ops {
-  const void* solve_fn;  // a forward kernel, for the occupancy query
+  // The forward kernel variants, [output nodes][tape], for the occupancy
+  // query of the one that runs.
+  const void* solve_fn[2][2];
   void (*solve)(const gs::Params&, int grid, int block, hipStream_t);
   // grid <= 0: no launch; writes the blocks per CU of the variant that
   // would run to *V.occupancy_out.
