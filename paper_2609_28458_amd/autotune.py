@@ -15,6 +15,7 @@ import json
 import math
 import os
 
+import numpy as np
 import torch
 
 from . import api
@@ -122,6 +123,41 @@ def tune_forward(prob: api.Problem, order=None, base: api.Launch | None = None,
     if use_cache:
         _store(cache)
     return api.Launch(**{**base.__dict__, **best[1]})
+
+
+def _subset(prob: api.Problem, idx: torch.Tensor) -> api.Problem:
+    """The trajectories idx of prob (per-trajectory arrays sliced, shared ones kept)."""
+    n = prob.n
+
+    def cols(t):
+        if t is None:
+            return None
+        if t.dim() == 2 and t.shape[1] == n:
+            return t[:, idx].contiguous()
+        if t.dim() == 1 and t.numel() == n and n > 1:
+            return t[idx].contiguous()
+        return t
+    return api.Problem(prob.rhs, prob.tableau, cols(prob.y0), cols(prob.theta), cols(prob.t0),
+                       cols(prob.t1), cols(prob.rtol), cols(prob.atol), cols(prob.t_out))
+
+
+def pilot_order(prob: api.Problem, features, sample: int = 4096,
+                launch: api.Launch | None = None, seed: int = 0):
+    """Longest-first queue order from a pilot solve, for ensembles whose cost
+    has no closed-form model: a random sample of the trajectories is solved,
+    their step attempts are fitted by least squares on the features ([F][n]
+    host arrays, e.g. logarithms of parameters and spans), and every
+    trajectory is ordered by its fitted cost, largest first.  The pilot is
+    set-up work, like the launch-shape search."""
+    n = prob.n
+    rng = np.random.default_rng(seed)
+    idx = np.sort(rng.choice(n, min(sample, n), replace=False))
+    sub = _subset(prob, torch.as_tensor(idx, device=prob.y0.device))
+    sol = api.solve(sub, launch or api.Launch())
+    att = (sol.n_accepted + sol.n_rejected).double().cpu().numpy()
+    F = np.column_stack([np.ones(n)] + [np.asarray(f, float) for f in features])
+    coef, *_ = np.linalg.lstsq(F[idx], att, rcond=None)
+    return np.argsort(-(F @ coef), kind="stable").astype(np.int64)
 
 
 def tune_gradient(prob: api.Problem, make_cotangent, base: api.Launch | None = None,

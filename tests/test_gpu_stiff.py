@@ -168,3 +168,27 @@ def test_shared_parameters_and_output_times(orc):
     for k in a:
         np.testing.assert_array_equal(a[k], b[k], err_msg=k)
     _compare(a, _oracle(orc, shared))
+
+
+def test_pilot_fitted_order():
+    """autotune.pilot_order: a permutation of the trajectories, results in
+    that order bitwise those of index order, and on kin3 (whose cost is close
+    to log-linear in its inputs) a rank correlation with the run's own
+    attempt counts above 0.9."""
+    from scipy.stats import spearmanr
+
+    from paper_2609_28458_amd import autotune
+    w = inputs.kinetics3(n=20_000, seed=29, K=0)
+    p = api.make_problem(w["rhs"], "rodas4", w["y0"], w["theta"], w["t0"], w["t1"], w["rtol"],
+                         w["atol"])
+    feats = [np.log(r) for r in w["theta"]] + [np.log(w["t1"]), np.log(w["y0"][2])]
+    order = autotune.pilot_order(p, feats, sample=2048)
+    assert np.array_equal(np.sort(order), np.arange(20_000))
+    a = _gpu_solve(w)
+    b = _gpu_solve(w, order=order)
+    for k in a:
+        np.testing.assert_array_equal(b[k], a[k], err_msg=k)
+    att = a["n_accepted"] + a["n_rejected"]
+    rank = np.empty(20_000)
+    rank[order] = np.arange(20_000)
+    assert spearmanr(-rank, att).correlation > 0.9
