@@ -520,17 +520,24 @@ def main():
     cprob = api.make_problem(cw["rhs"], cw["tableau"], cw["y0"], cw["theta"], cw["t0"],
                              cw["t1"], cw["rtol"], cw["atol"], cw["t_out"])
     corder = np.argsort(-inputs.predicted_cost(cw), kind="stable")
-    csol = api.Solution(cprob, autotune.tune_forward(cprob, order=corder, use_cache=False))
+    claunch = autotune.tune_forward(cprob, order=corder, use_cache=False)
+    csol = api.Solution(cprob, claunch)
+    csol.set_order(corder)
+    ms_dkn = timed(lambda: csol.run(), 3, 1, torch)
+    att_c = int((csol.n_accepted + csol.n_rejected).to(torch.int64).sum())
+    del csol
+    # the same with each trajectory's components of an output adjacent in y_out
+    csol = api.Solution(cprob, api.Launch(**{**claunch.__dict__, "out_layout": "knd"}))
     csol.set_order(corder)
     ms_c = timed(lambda: csol.run(), 3, 1, torch)
-    att_c = int((csol.n_accepted + csol.n_rejected).to(torch.int64).sum())
     fl_c = (att_c * FLOPS_PER_ATTEMPT[("dopri5", "loghalo")]
             + nc * cprob.K * FLOPS_PER_NODE[("dopri5", "loghalo")])
     ach_c = fl_c / (ms_c * 1e-3) / 1e12
     c1_million = {"workload": "1,000,000 orbits of the 1,000-orbit forward recipe: shared halo, "
                               "Dopri5 1e-8/1e-10, 64 outputs to t = 50, longest-first",
                   "launch": {k: csol.launch.__dict__[k] for k in ("block", "grid", "refill")},
-                  "ms": round(ms_c, 3), "attempts": att_c,
+                  "out_layout": "[K][n][d]", "ms": round(ms_c, 3),
+                  "ms_out_layout_dkn": round(ms_dkn, 3), "attempts": att_c,
                   "flops_per_attempt": FLOPS_PER_ATTEMPT[("dopri5", "loghalo")],
                   "flops_per_output": FLOPS_PER_NODE[("dopri5", "loghalo")],
                   "output_gb_per_s": round(6 * cprob.K * nc * 8 / (ms_c * 1e-3) / 1e9, 1),
@@ -538,7 +545,7 @@ def main():
                   "frac": round(ach_c / PEAK_FP64_VECTOR_TFLOPS, 4),
                   "all_ok": bool((csol.status == 0).all())}
     log(f"[bench] 10^6 orbits, 64 outputs: {ms_c:.3f} ms, {ach_c:.2f} TFLOP/s "
-        f"({100 * ach_c / PEAK_FP64_VECTOR_TFLOPS:.1f}%)")
+        f"({100 * ach_c / PEAK_FP64_VECTOR_TFLOPS:.1f}%); [d][K][n] outputs {ms_dkn:.3f} ms")
     del csol
     torch.cuda.empty_cache()
     log(f"[bench] kernel {ms_kernel:.3f} ms = {achieved:.2f} TFLOP/s; lone wave "

@@ -186,6 +186,13 @@ typedef struct gs_solve_args {
                             (diagnostic; reset by each gs_solve_vjp).      */
   size_t workspace_bytes;
   void* stream;          /* hipStream_t                                     */
+  int32_t out_layout;    /* layout of y_out: 0 = [d][K][n] (the default);
+                            1 = [K][n][d], the d components of one output of
+                            one trajectory adjacent, so an output costs one
+                            cache line in HBM instead of d.  Explicit
+                            tableaux only (GS_RODAS4 with 1:
+                            GS_ERR_UNSUPPORTED); any other value:
+                            GS_ERR_INVALID.                                 */
 } gs_solve_args;
 
 /* Cotangents for gs_solve_vjp.  R independent scalar losses over the same

@@ -28,6 +28,7 @@ DIM = {0: 2, 1: 4, 2: 6, 3: 9, 4: 3, 5: 3, 6: 8}
 NPARAM = {0: 1, 1: 1, 2: 3, 3: 3, 4: 4, 5: 3, 6: 12}
 TABLEAU = {"dopri5": 0, "tsit5": 1, "verner7": 2, "rodas4": 3}
 SCHEDULE = {"queue": 0, "static": 1}
+OUT_LAYOUT = {"dkn": 0, "knd": 1}
 TRAJ_STATUS = {0: "OK", 1: "MAX_STEPS", 2: "DT_UNDERFLOW", 3: "NONFINITE",
                4: "TAPE_OVERFLOW", 5: "BAD_INPUT"}
 GS_OK = 0
@@ -57,6 +58,7 @@ class gs_solve_args(C.Structure):
         ("schedule", C.c_int32), ("block", C.c_int32), ("grid", C.c_int32),
         ("refill", C.c_int32), ("wide", C.c_int32), ("order", C.c_void_p),
         ("workspace", C.c_void_p), ("workspace_bytes", C.c_size_t), ("stream", C.c_void_p),
+        ("out_layout", C.c_int32),
     ]
 
 
@@ -84,6 +86,7 @@ class gs_de_profile_args(C.Structure):
         ("atol", C.c_double), ("chi2", C.c_void_p), ("chi2_prev", C.c_void_p),
         ("decrement", C.c_void_p), ("dist", C.c_void_p), ("status", C.c_void_p),
         ("workspace", C.c_void_p), ("workspace_bytes", C.c_size_t), ("stream", C.c_void_p),
+        ("out_layout", C.c_int32),
     ]
 
 
@@ -277,6 +280,7 @@ class Launch:
     alpha_max: float = 5.0
     beta1: float = 0.0
     beta2: float = 0.0
+    out_layout: str = "dkn"  # y_out [d][K][n]; "knd": [K][n][d]
 
 
 def workspace_bytes(prob: Problem, launch: Launch) -> int:
@@ -295,7 +299,8 @@ class Solution:
         n, d, K = prob.n, prob.d, prob.K
         self.prob = prob
         self.launch = launch
-        self.y_out = torch.empty((d, K, n), dtype=torch.float64, device=dev) if K else None
+        shape = (K, n, d) if launch.out_layout == "knd" else (d, K, n)
+        self.y_out = torch.empty(shape, dtype=torch.float64, device=dev) if K else None
         self.y_final = torch.empty((d, n), dtype=torch.float64, device=dev)
         self.n_accepted = torch.empty(n, dtype=torch.int32, device=dev)
         self.n_rejected = torch.empty(n, dtype=torch.int32, device=dev)
@@ -332,6 +337,7 @@ class Solution:
         a.ckpt_every, a.ckpt_capacity = L.ckpt_every, L.ckpt_capacity
         a.schedule = SCHEDULE[L.schedule]
         a.block, a.grid, a.refill, a.wide = L.block, L.grid, L.refill, L.wide
+        a.out_layout = OUT_LAYOUT[L.out_layout]
         return a
 
     def set_order(self, order):

@@ -117,6 +117,7 @@ gs_status check_args(const gs_solve_args* a) {
   if (a->grid < 0) return GS_ERR_INVALID;
   if (a->refill < 0 || a->refill > 64) return GS_ERR_INVALID;
   if (a->wide < 0) return GS_ERR_INVALID;
+  if (a->out_layout != 0 && a->out_layout != 1) return GS_ERR_INVALID;
   if (a->wide > 0 && (a->schedule != GS_SCHED_QUEUE || a->K > 0 || a->ckpt_every > 0))
     return GS_ERR_UNSUPPORTED;
   const gs_controller& c = a->ctrl;
@@ -124,7 +125,8 @@ gs_status check_args(const gs_solve_args* a) {
       !(c.alpha_min <= 1.0))
     return GS_ERR_INVALID;
   if ((a->rhs >= kNumExplicitRhs) != is_stiff(a)) return GS_ERR_UNSUPPORTED;
-  if (is_stiff(a) && (a->ckpt_every > 0 || a->wide > 0 || c.beta1 > 0.0 || c.beta2 != 0.0))
+  if (is_stiff(a) && (a->ckpt_every > 0 || a->wide > 0 || a->out_layout != 0 || c.beta1 > 0.0 ||
+                      c.beta2 != 0.0))
     return GS_ERR_UNSUPPORTED;
   if (!a->workspace) return GS_ERR_WORKSPACE;
   if (a->workspace_bytes < layout_of(a).total) return GS_ERR_WORKSPACE;
@@ -136,6 +138,7 @@ Params make_params(const gs_solve_args* a) {
   Params P;
   std::memset(&P, 0, sizeof P);
   P.n = a->n;
+  P.out_layout = a->out_layout;
   P.y0 = a->y0;
   P.theta = a->theta;
   P.theta_stride = a->theta_stride;

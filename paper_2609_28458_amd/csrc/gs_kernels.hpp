@@ -116,6 +116,7 @@ struct Params {
   int32_t fast_ctrl;  // I controller with default exponent and alpha in [0.01, 100]
   int64_t n_wide;     // queue positions [0, n_wide) run 16 lanes per trajectory
   int32_t wide_blocks;  // the first wide_blocks workgroups run those
+  int32_t out_layout;   // y_out: 0 = [d][K][n], 1 = [K][n][d]
 };
 
 struct VjpParams {
@@ -962,7 +963,8 @@ __device__ __forceinline__ void forward_body(const Params& P, const SensParams& 
   auto put_node = [&](int kk, const T (&v)[D]) {
 #pragma unroll
     for (int c = 0; c < D; ++c) {
-      P.y_out[((int64_t)c * P.K + kk) * P.n + idx] = ad::val(v[c]);
+      P.y_out[P.out_layout ? ((int64_t)kk * P.n + idx) * D + c
+                           : ((int64_t)c * P.K + kk) * P.n + idx] = ad::val(v[c]);
       if constexpr (SENS) {
 #pragma unroll
         for (int m = 0; m < M; ++m)

@@ -166,9 +166,10 @@ def test_stiff_path_argument_checks():
     assert L.gs_solve(C.byref(_args(tableau=3))) == 2
     assert L.gs_solve(C.byref(_stiff(d=8))) == 1
     assert L.gs_solve(C.byref(_stiff(rhs=6, d=8, p=11))) == 1
-    # no tape, no wide groups, I control only
+    # no tape, no wide groups, the default output layout, I control only
     assert L.gs_solve(C.byref(_stiff(ckpt_every=1, ckpt_capacity=10))) == 2
     assert L.gs_solve(C.byref(_stiff(wide=4))) == 2
+    assert L.gs_solve(C.byref(_stiff(out_layout=1))) == 2
     b = _stiff()
     b.ctrl.beta2 = 0.04
     assert L.gs_solve(C.byref(b)) == 2
@@ -192,3 +193,12 @@ def test_size_limits():
     assert L.gs_rhs_eval(2, (1 << 31) + 1, 0x1000, 0x1000, 0x1000, 0x1000, None, None, None,
                          None) == 2
     assert L.gs_solve(C.byref(_args(n=(1 << 31) + 1))) == 2
+
+
+def test_output_layout_argument():
+    """out_layout is 0 ([d][K][n]) or 1 ([K][n][d]); anything else is rejected
+    before a launch."""
+    L = api.lib()
+    for bad in (-1, 2, 7):
+        assert L.gs_solve(C.byref(_args(out_layout=bad))) == 1
+    assert api.OUT_LAYOUT == {"dkn": 0, "knd": 1}

@@ -232,3 +232,21 @@ def test_wide_groups_with_a_small_grid(grid, wide):
     assert np.all(ref["status"] == 0)
     for k in ref:
         np.testing.assert_array_equal(g[k], ref[k], err_msg=k)
+
+
+@pytest.mark.parametrize("tab", ["dopri5", "tsit5", "verner7"])
+def test_output_layout_knd(tab):
+    """y_out in [K][n][d] holds the default [d][K][n] outputs transposed, bit
+    for bit, for polynomial and shortened-step outputs, shared and
+    per-trajectory output times, and the NaN outputs of trajectories stopped
+    before them."""
+    w = {**inputs.orbits_forward(300, seed=50), "tableau": tab}
+    tk = np.sort(np.random.default_rng(51).uniform(0.0, 50.0, (24, 300)), axis=0)
+    for wt in (w, {**w, "t_out": tk}):
+        for L0, L1 in ((api.Launch(), api.Launch(out_layout="knd")),
+                       (api.Launch(max_steps=300), api.Launch(max_steps=300, out_layout="knd"))):
+            a = to_np(gpu_solve(wt, L0))
+            b = to_np(gpu_solve(wt, L1))
+            np.testing.assert_array_equal(b["y_out"], a["y_out"].transpose(1, 2, 0))
+            for k in ("y_final", "n_accepted", "n_rejected", "status"):
+                np.testing.assert_array_equal(b[k], a[k], err_msg=k)
