@@ -611,26 +611,56 @@ def main():
         wg = inputs.orbits_gradient(n=args.n)
         pg = api.make_problem(wg["rhs"], wg["tableau"], wg["y0"], wg["theta"], wg["t0"],
                               wg["t1"], wg["rtol"], wg["atol"])
-        plain = api.Solution(pg, api.Launch(block=256))
-        ms_fwd = timed(lambda: plain.run(), max(3, args.steps // 4), 1, torch)
+        reps = max(3, args.steps // 4)
+        gorder = np.argsort(-inputs.predicted_cost(wg), kind="stable")
         T = torch.as_tensor(wg["targets"], device="cuda")
-        best = None
-        per_k = {}
-        for k in (1, 8, 32, 128):
-            cap = int(plain.n_accepted.max()) // k + 2
-            taped = api.Solution(pg, api.Launch(block=256, ckpt_every=k, ckpt_capacity=cap))
-            ybf = torch.zeros((1, 6, pg.n), dtype=torch.float64, device="cuda")
+        # The forward alone at its best: the tuned launch (groups allowed), longest first.
+        flaunch = autotune.tune_forward(pg, order=gorder, use_cache=False)
+        plain = api.Solution(pg, flaunch)
+        plain.set_order(gorder)
+        ms_fwd = timed(lambda: plain.run(), reps, 1, torch)
+        nmax = int(plain.n_accepted.max())
+        cus = torch.cuda.get_device_properties(0).multi_processor_count
+        ybf = torch.zeros((1, 6, pg.n), dtype=torch.float64, device="cuda")
+
+        def grad_ms(block, grid, k, order):
+            """Forward with tape, then the adjoint, in one launch shape."""
+            taped = api.Solution(pg, api.Launch(block=block, grid=grid, ckpt_every=k,
+                                                ckpt_capacity=nmax // k + 2))
+            if order is not None:
+                taped.set_order(order)
 
             def grad_step():
                 taped.run()
                 ybf[0, :3] = 2.0 * (taped.y_final[:3] - T)
-                api.solve_vjp(taped, ybar_final=ybf)
+                api.solve_vjp(taped, ybar_final=ybf, block=block, grid=grid)
 
-            ms_g = timed(grad_step, max(3, args.steps // 4), 1, torch)
-            per_k[k] = round(ms_g, 4)
-            if best is None or ms_g < best[1]:
-                best = (k, ms_g)
-        log(f"[bench] gradient: forward {ms_fwd:.3f} ms, with tape + adjoint {per_k}")
+            return timed(grad_step, reps, 1, torch)
+
+        # The gradient at its best: store-mode tape in launch shapes with one or two waves
+        # per SIMD (the persistent queues refill them), index or longest-first order; then
+        # the checkpoint interval k in the best shape.
+        shapes = {"block 256, occupancy grid, index order": (256, 0, None),
+                  "block 256, occupancy grid, longest first": (256, 0, gorder),
+                  "block 128, 2 waves per CU, longest first": (128, 2 * cus, gorder),
+                  "block 64, 1 wave per SIMD, longest first": (64, 4 * cus, gorder),
+                  "block 256, 1 wave per SIMD, longest first": (256, cus, gorder)}
+        by_shape = {name: round(grad_ms(sh[0], sh[1], 1, sh[2]), 4) for name, sh in shapes.items()}
+        gshape = min(by_shape, key=by_shape.get)
+        gb, gg, go = shapes[gshape]
+        per_k = {1: by_shape[gshape]}
+        for k in (8, 32, 128):
+            per_k[k] = round(grad_ms(gb, gg, k, go), 4)
+        best = min(per_k.items(), key=lambda kv: kv[1])
+        # the forward in the gradient's launch shape, for the ratio within one launch
+        same = api.Solution(pg, api.Launch(block=gb, grid=gg))
+        if go is not None:
+            same.set_order(go)
+        ms_fwd_same = timed(lambda: same.run(), reps, 1, torch)
+        del same
+        log(f"[bench] gradient: forward {ms_fwd:.3f} ms (tuned, longest first), gradient "
+            f"{best[1]:.3f} ms ({gshape}, k = {best[0]}), by shape {by_shape}, by k {per_k}; "
+            f"forward in that shape {ms_fwd_same:.3f} ms")
         # The plain arm: one lane per trajectory in both passes (static forward with the
         # store-mode tape; an adjoint grid with exactly one lane for every trajectory).
         cap1 = int(plain.n_accepted.max()) + 2
@@ -708,6 +738,11 @@ def main():
         del vsol, vyb
         torch.cuda.empty_cache()
         out["grad"] = {"workload": "orbits_gradient_100k", "ms_forward": round(ms_fwd, 4),
+                       "forward_launch": {k: flaunch.__dict__[k]
+                                          for k in ("block", "grid", "refill", "wide")},
+                       "gradient_launch": gshape, "ms_gradient_by_launch": by_shape,
+                       "ms_forward_in_gradient_launch": round(ms_fwd_same, 4),
+                       "grad_forward_ratio_same_launch": round(best[1] / ms_fwd_same, 3),
                        "vjp_roofline": vjp_roofline,
                        "ms_forward_tape_plus_vjp": round(best[1], 4), "ckpt_every": best[0],
                        "ms_by_ckpt_every": per_k,
@@ -747,10 +782,12 @@ def main():
         del ufused, ustat
         out["grad_forward_ratio"] = best[1] / ms_fwd
         # The paper's own derivative: forward sensitivities in the same launch,
-        # two columns (v0, q) as in its stream gradients, and all nine inputs.
+        # two columns (v0, q) as in its stream gradients, and all nine inputs
+        # (longest first; the ratio is to the best forward).
         sens = {}
         for cols in ([6, 7], list(range(9))):
-            ms_s = timed(lambda: api.solve_sens(pg, cols), max(3, args.steps // 4), 1, torch)
+            ms_s = timed(lambda: api.solve_sens(pg, cols, order=gorder), max(3, args.steps // 4),
+                         1, torch)
             sens[str(len(cols))] = {"ms": round(ms_s, 4), "ratio": round(ms_s / ms_fwd, 3)}
         out["grad"]["forward_sensitivities_by_columns"] = sens
         log(f"[bench] forward sensitivities: {sens}")

@@ -365,11 +365,14 @@ def gs_solve_sens(args: gs_solve_args, sens: gs_sens_args) -> None:
     _check(lib().gs_solve_sens(C.byref(args), C.byref(sens)))
 
 
-def solve_sens(prob: Problem, cols, launch: Launch | None = None, stream=None):
+def solve_sens(prob: Problem, cols, launch: Launch | None = None, stream=None, order=None):
     """Solution plus forward sensitivities (eq:sens) of the columns ``cols``:
     index c < d is y0[c], d + q is theta[q].  Returns (Solution, S_final
-    [d][M][n], S_out [d][M][K][n] or None)."""
+    [d][M][n], S_out [d][M][K][n] or None).  ``order``: queue order, as for
+    solve."""
     sol = Solution(prob, launch or Launch())
+    if order is not None:
+        sol.set_order(order)
     cols = [int(c) for c in cols]
     M = len(cols)
     dev = prob.y0.device
