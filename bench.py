@@ -623,10 +623,10 @@ def main():
         cus = torch.cuda.get_device_properties(0).multi_processor_count
         ybf = torch.zeros((1, 6, pg.n), dtype=torch.float64, device="cuda")
 
-        def grad_ms(block, grid, k, order):
+        def grad_ms(block, grid, k, order, wide=0):
             """Forward with tape, then the adjoint, in one launch shape."""
             taped = api.Solution(pg, api.Launch(block=block, grid=grid, ckpt_every=k,
-                                                ckpt_capacity=nmax // k + 2))
+                                                ckpt_capacity=nmax // k + 2, wide=wide))
             if order is not None:
                 taped.set_order(order)
 
@@ -638,22 +638,28 @@ def main():
             return timed(grad_step, reps, 1, torch)
 
         # The gradient at its best: store-mode tape in launch shapes with one or two waves
-        # per SIMD (the persistent queues refill them), index or longest-first order; then
-        # the checkpoint interval k in the best shape.
-        shapes = {"block 256, occupancy grid, index order": (256, 0, None),
-                  "block 256, occupancy grid, longest first": (256, 0, gorder),
-                  "block 128, 2 waves per CU, longest first": (128, 2 * cus, gorder),
-                  "block 64, 1 wave per SIMD, longest first": (64, 4 * cus, gorder),
-                  "block 256, 1 wave per SIMD, longest first": (256, cus, gorder)}
-        by_shape = {name: round(grad_ms(sh[0], sh[1], 1, sh[2]), 4) for name, sh in shapes.items()}
+        # per SIMD (the persistent queues refill them), index or longest-first order, the
+        # head of the order on 16-lane groups (which write the store-mode tape too); then
+        # the checkpoint interval k in the best shape (single lanes only).
+        shapes = {"block 256, occupancy grid, index order": (256, 0, None, 0),
+                  "block 256, occupancy grid, longest first": (256, 0, gorder, 0),
+                  "block 128, 2 waves per CU, longest first": (128, 2 * cus, gorder, 0),
+                  "block 64, 1 wave per SIMD, longest first": (64, 4 * cus, gorder, 0),
+                  "block 256, 1 wave per SIMD, longest first": (256, cus, gorder, 0),
+                  "block 128, 2 waves per CU, longest first, 256 on groups":
+                      (128, 2 * cus, gorder, 256),
+                  "block 64, 1 wave per SIMD, longest first, 256 on groups":
+                      (64, 4 * cus, gorder, 256)}
+        by_shape = {name: round(grad_ms(sh[0], sh[1], 1, sh[2], sh[3]), 4)
+                    for name, sh in shapes.items()}
         gshape = min(by_shape, key=by_shape.get)
-        gb, gg, go = shapes[gshape]
+        gb, gg, go, gw = shapes[gshape]
         per_k = {1: by_shape[gshape]}
         for k in (8, 32, 128):
             per_k[k] = round(grad_ms(gb, gg, k, go), 4)
         best = min(per_k.items(), key=lambda kv: kv[1])
         # the forward in the gradient's launch shape, for the ratio within one launch
-        same = api.Solution(pg, api.Launch(block=gb, grid=gg))
+        same = api.Solution(pg, api.Launch(block=gb, grid=gg, wide=gw))
         if go is not None:
             same.set_order(go)
         ms_fwd_same = timed(lambda: same.run(), reps, 1, torch)

@@ -803,8 +803,10 @@ __device__ __forceinline__ Attempt group_attempt(const Params& P, const GroupCoe
 // queue positions [0, n_wide) (the head of the order, longest first when
 // the caller sorts by predicted cost), one per 16-lane group, from their own
 // queue head (counters[3]).  Control mirrors the single-lane loop; every
-// ballot sits where all lanes of the wave execute it.
-template <class TB, class F>
+// ballot sits where all lanes of the wave execute it.  TAPE: a store-mode
+// tape (every accepted step), written as one lane writes it: lane c of the
+// group stores component c of each record, lane 0 its time and step.
+template <class TB, class F, bool TAPE>
 __device__ void solve_group(const Params& P) {
   constexpr int D = F::D;
   const int lane = threadIdx.x & 63;
@@ -814,21 +816,30 @@ __device__ void solve_group(const Params& P) {
   GroupCoef<TB> cf;
   cf.load();
   int64_t idx = -1;
-  bool live = false;
+  bool live = false, overflow = false;
   bool queue_empty = false;
 
+  auto put_record = [&](int n, double h_in) {
+    double* r = P.tape + ((int64_t)idx * P.ckpt_cap + n) * store_record_len<F>();
+    if (c < D) r[2 + c] = s.y;
+    if (c == 0) {
+      r[0] = s.t;
+      r[1] = h_in;
+    }
+  };
   auto finish = [&](int32_t st) {
     if (c < D) P.y_final[(int64_t)c * P.n + idx] = s.y;
     if (c == 0) {
       P.n_acc[idx] = s.nacc;
       P.n_rej[idx] = s.nrej;
-      P.status[idx] = st;
+      P.status[idx] = (st == ST_OK && overflow) ? ST_TAPE_OVERFLOW : st;
     }
     live = false;
   };
   auto start = [&](int64_t i) {
     idx = i;
     live = true;
+    overflow = false;
     s.nacc = s.nrej = s.nanrun = 0;
     s.err_prev2 = 1.0;
     double y0[D];
@@ -854,6 +865,12 @@ __device__ void solve_group(const Params& P) {
     F::f(s.t, y0, s.in.par, f0);
     s.k[0] = c < D ? pick<D>(f0, c) : 0.0;
     s.h = P.h0 > 0.0 ? dmin(P.h0, s.in.t1 - s.in.t0) : initial_step<TB, F>(s.in, y0, f0);
+    if constexpr (TAPE) {
+      if (P.ckpt_cap <= 0)
+        overflow = true;
+      else
+        put_record(0, 0.0);
+    }
   };
 
   for (;;) {
@@ -887,6 +904,15 @@ __device__ void solve_group(const Params& P) {
           st = ST_MAX_STEPS;
         } else {
           const Attempt a = group_attempt<TB, F>(P, cf, s, c);
+          if constexpr (TAPE) {
+            // every accepted step, the last one included
+            if (a.accepted) {
+              if (s.nacc < P.ckpt_cap)
+                put_record(s.nacc, a.h_used);
+              else
+                overflow = true;
+            }
+          }
           if (a.finished) st = a.status;
         }
       }
@@ -1148,9 +1174,9 @@ __device__ __forceinline__ void forward_body(const Params& P, const SensParams& 
 template <class TB, class F, bool NODES, bool TAPE>
 __global__ void __launch_bounds__(256)
     __attribute__((amdgpu_waves_per_eu(FwdOccupancy<TB, F>::waves, 8))) solve_kernel(Params P) {
-  if constexpr (!NODES && !TAPE && F::D <= kGroup) {
+  if constexpr (!NODES && F::D <= kGroup) {
     if ((int)blockIdx.x < P.wide_blocks) {  // uniform per workgroup
-      solve_group<TB, F>(P);
+      solve_group<TB, F, TAPE>(P);
       return;
     }
   }

@@ -250,3 +250,38 @@ def test_output_layout_knd(tab):
             np.testing.assert_array_equal(b["y_out"], a["y_out"].transpose(1, 2, 0))
             for k in ("y_final", "n_accepted", "n_rejected", "status"):
                 np.testing.assert_array_equal(b[k], a[k], err_msg=k)
+
+
+def test_wide_groups_write_the_store_tape():
+    """Groups with a store-mode tape: the tape bytes, results and statuses of
+    one lane per trajectory, and the same adjoint gradients from it; with a
+    tape too short, the same overflow status."""
+    w = inputs.orbits_uneven(n=3000, seed=52)
+    w = {**w, "t1": np.minimum(w["t1"], 60.0)}
+    order = np.argsort(-inputs.predicted_cost(w), kind="stable")
+    p = api.make_problem(w["rhs"], w["tableau"], w["y0"], w["theta"], w["t0"], w["t1"],
+                         w["rtol"], w["atol"])
+    nmax = int(api.solve(p).n_accepted.max())
+    for cap in (nmax + 2, 40):
+        sols = []
+        for wide in (0, 500):
+            s = api.Solution(p, api.Launch(block=128, ckpt_every=1, ckpt_capacity=cap, wide=wide))
+            s.set_order(order)
+            s.workspace.zero_()  # records past a trajectory's last step are never written
+            s.run()
+            sols.append(s)
+        torch.cuda.synchronize()
+        a, b = sols
+        for k in ("y_final", "n_accepted", "n_rejected", "status"):
+            assert torch.equal(getattr(a, k), getattr(b, k)), k
+        tape_bytes = 3000 * cap * (2 + 6) * 8
+        assert torch.equal(a.workspace[256:256 + tape_bytes], b.workspace[256:256 + tape_bytes])
+        if cap == 40:
+            assert bool((a.status == 4).any())
+            continue
+        assert bool((a.status == 0).all())
+        yb = torch.ones((1, 6, 3000), dtype=torch.float64, device="cuda")
+        ga = api.solve_vjp(a, ybar_final=yb)
+        gb = api.solve_vjp(b, ybar_final=yb)
+        for x, y in zip(ga, gb):
+            assert torch.equal(x, y)
