@@ -126,19 +126,17 @@ def tune_forward(prob: api.Problem, order=None, base: api.Launch | None = None,
 
 
 def _subset(prob: api.Problem, idx: torch.Tensor) -> api.Problem:
-    """The trajectories idx of prob (per-trajectory arrays sliced, shared ones kept)."""
-    n = prob.n
+    """The trajectories idx of prob.  Per-trajectory arrays are sliced and shared
+    ones kept, by their role: y0 [d][n]; theta [p][n] or shared [p]; t0, t1,
+    rtol, atol [n] or shared [1]; t_out [K][n] or shared [K]."""
+    def per_traj_2d(t):
+        return None if t is None else (t[:, idx].contiguous() if t.dim() == 2 else t)
 
-    def cols(t):
-        if t is None:
-            return None
-        if t.dim() == 2 and t.shape[1] == n:
-            return t[:, idx].contiguous()
-        if t.dim() == 1 and t.numel() == n and n > 1:
-            return t[idx].contiguous()
-        return t
-    return api.Problem(prob.rhs, prob.tableau, cols(prob.y0), cols(prob.theta), cols(prob.t0),
-                       cols(prob.t1), cols(prob.rtol), cols(prob.atol), cols(prob.t_out))
+    def per_traj_1d(t):
+        return t[idx].contiguous() if t.numel() == prob.n and t.numel() > 1 else t
+    return api.Problem(prob.rhs, prob.tableau, per_traj_2d(prob.y0), per_traj_2d(prob.theta),
+                       per_traj_1d(prob.t0), per_traj_1d(prob.t1), per_traj_1d(prob.rtol),
+                       per_traj_1d(prob.atol), per_traj_2d(prob.t_out))
 
 
 def pilot_order(prob: api.Problem, features, sample: int = 4096,
@@ -150,12 +148,15 @@ def pilot_order(prob: api.Problem, features, sample: int = 4096,
     trajectory is ordered by its fitted cost, largest first.  The pilot is
     set-up work, like the launch-shape search."""
     n = prob.n
+    feats = [np.asarray(f, float).reshape(-1) for f in features]
+    if any(f.shape != (n,) or not np.all(np.isfinite(f)) for f in feats):
+        raise ValueError("features must be finite arrays of one value per trajectory")
     rng = np.random.default_rng(seed)
     idx = np.sort(rng.choice(n, min(sample, n), replace=False))
     sub = _subset(prob, torch.as_tensor(idx, device=prob.y0.device))
     sol = api.solve(sub, launch or api.Launch())
     att = (sol.n_accepted + sol.n_rejected).double().cpu().numpy()
-    F = np.column_stack([np.ones(n)] + [np.asarray(f, float) for f in features])
+    F = np.column_stack([np.ones(n)] + feats)
     coef, *_ = np.linalg.lstsq(F[idx], att, rcond=None)
     return np.argsort(-(F @ coef), kind="stable").astype(np.int64)
 
