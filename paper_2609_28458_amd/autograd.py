@@ -68,7 +68,9 @@ class GsSolveFn(torch.autograd.Function):
         yf = None if g_final is None else g_final.contiguous().unsqueeze(0)
         if yo is None and yf is None:
             return None, None, None
-        y0bar, thbar = api.solve_vjp(sol, ybar_final=yf, ybar_out=yo)
+        # the adjoint in the forward's launch shape (as tune_gradient times it)
+        y0bar, thbar = api.solve_vjp(sol, ybar_final=yf, ybar_out=yo, block=sol.launch.block,
+                                     grid=sol.launch.grid)
         thbar = thbar[0]
         if ctx.shared_theta:
             thbar = thbar.sum(dim=1)

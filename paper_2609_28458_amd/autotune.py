@@ -162,12 +162,16 @@ def pilot_order(prob: api.Problem, features, sample: int = 4096,
 
 
 def tune_gradient(prob: api.Problem, make_cotangent, base: api.Launch | None = None,
-                  use_cache=True) -> api.Launch:
-    """Fastest checkpoint interval for forward-with-tape plus adjoint.
+                  use_cache=True, order=None) -> api.Launch:
+    """Fastest launch for forward-with-tape plus adjoint: the checkpoint
+    interval k, and the launch shape of both passes (the base shape, two
+    waves per CU, one wave per SIMD; with a queue order and a store-mode
+    tape also the head of the order on 16-lane groups).  Run the adjoint
+    with the returned block and grid (``solve_vjp(..., block=, grid=)``).
 
     ``make_cotangent(sol)`` returns (ybar_final, ybar_out) for a solution.
     """
-    key = _key(prob, "grad")
+    key = _key(prob, "grad" if order is None else "grad-ordered")
     cache = _load() if use_cache else {}
     base = base or api.Launch()
     if key in cache:
@@ -175,22 +179,35 @@ def tune_gradient(prob: api.Problem, make_cotangent, base: api.Launch | None = N
     plain = api.solve(prob, base)
     torch.cuda.synchronize()
     nmax = int(plain.n_accepted.max())
+    cus = torch.cuda.get_device_properties(prob.y0.device).multi_processor_count
+    shapes = [(base.block, base.grid, 0), (128, 2 * cus, 0), (64, 4 * cus, 0)]
+    if (order is not None and prob.K == 0 and prob.d <= 16
+            and prob.tableau != api.TABLEAU["rodas4"]):
+        shapes.append((128, 2 * cus, 256))
     best = None
     free = torch.cuda.mem_get_info(prob.y0.device)[0]
-    for k in CKPT:
-        L = api.Launch(**{**base.__dict__, "ckpt_every": k, "ckpt_capacity": nmax // k + 2})
-        if api.workspace_bytes(prob, L) > free // 2:
-            continue  # the tape would crowd out everything else
-        sol = api.Solution(prob, L)
+    for block, grid, wide in shapes:
+        for k in CKPT:
+            if wide and k != 1:
+                continue  # groups write the store-mode tape only
+            shape = {"block": block, "grid": grid, "wide": wide, "ckpt_every": k,
+                     "ckpt_capacity": nmax // k + 2}
+            L = api.Launch(**{**base.__dict__, **shape})
+            if api.workspace_bytes(prob, L) > free // 2:
+                continue  # the tape would crowd out everything else
+            sol = api.Solution(prob, L)
+            if order is not None:
+                sol.set_order(order)
 
-        def step():
-            sol.run()
-            yf, yo = make_cotangent(sol)
-            api.solve_vjp(sol, ybar_final=yf, ybar_out=yo)
+            def step():
+                sol.run()
+                yf, yo = make_cotangent(sol)
+                api.solve_vjp(sol, ybar_final=yf, ybar_out=yo, block=block, grid=grid)
 
-        ms = _time(step)
-        if best is None or ms < best[0]:
-            best = (ms, {"ckpt_every": k, "ckpt_capacity": nmax // k + 2})
+            ms = _time(step)
+            if best is None or ms < best[0]:
+                best = (ms, shape)
+            del sol
     cache[key] = {"ms": best[0], "launch": best[1]}
     if use_cache:
         _store(cache)

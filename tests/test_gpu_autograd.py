@@ -75,3 +75,16 @@ def test_autotuned_launch_gives_identical_results(tmp_path, monkeypatch):
 
     G = autotune.tune_gradient(prob, cot)
     assert G.ckpt_every in autotune.CKPT
+    # with a queue order the search also covers groups; the gradient it times is the
+    # default launch's
+    order = np.argsort(-inputs.predicted_cost(w), kind="stable")
+    G2 = autotune.tune_gradient(prob, cot, use_cache=False, order=order)
+    s2 = api.Solution(prob, G2)
+    s2.set_order(order)
+    s2.run()
+    g2 = api.solve_vjp(s2, ybar_final=cot(s2)[0], block=G2.block, grid=G2.grid)
+    s0 = api.Solution(prob, api.Launch(ckpt_every=1, ckpt_capacity=G2.ckpt_capacity * G2.ckpt_every))
+    s0.run()
+    g0 = api.solve_vjp(s0, ybar_final=cot(s0)[0])
+    for x, y in zip(g2, g0):
+        torch.testing.assert_close(x, y, rtol=1e-12, atol=0.0)
