@@ -26,7 +26,9 @@ Also reported on the same line:
 
 Modes: `--mode profile` runs the headline steps only (for rocprofv3 kernel
 traces); `--mode traffic` runs one device copy of known size and one headline
-solve (for rocprofv3 FETCH_SIZE / WRITE_SIZE passes).
+solve (for rocprofv3 FETCH_SIZE / WRITE_SIZE passes); `--mode lone` runs the
+batch's longest orbit alone on one lane and on one 16-lane group (for
+per-dispatch instruction counters).
 """
 from __future__ import annotations
 
@@ -86,7 +88,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=100_000)
-    ap.add_argument("--mode", choices=("full", "profile", "traffic"), default="full")
+    ap.add_argument("--mode", choices=("full", "profile", "traffic", "lone"), default="full")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-grad", action="store_true", help="skip the gradient ratio")
     ap.add_argument("--no-arms", action="store_true", help="skip the static and bucket arms")
@@ -422,6 +424,25 @@ def main():
     dev_name = torch.cuda.get_device_name(0)
     w, prob, order = headline(args, torch, api, inputs, autotune)
     n = prob.n
+
+    if args.mode == "lone":
+        # The batch's longest orbit alone, once on one lane and once on one 16-lane group
+        # (for per-dispatch instruction counters: two dispatches of one wavefront each).
+        sol = api.Solution(prob, profile_launch(api))
+        sol.set_order(order)
+        sol.run()
+        i_long = int(torch.argmax(sol.n_accepted + sol.n_rejected))
+        one = {k: (v[..., [i_long]] if isinstance(v, np.ndarray) and v.shape[-1:] == (n,)
+                   else v) for k, v in w.items()}
+        lprob = api.make_problem(one["rhs"], one["tableau"], one["y0"], one["theta"], one["t0"],
+                                 one["t1"], one["rtol"], one["atol"])
+        torch.cuda.synchronize()
+        for wide in (0, 1):
+            s1 = api.Solution(lprob, api.Launch(block=64, wide=wide))
+            s1.run()
+            torch.cuda.synchronize()
+            print(json.dumps({"wide": wide, "attempts": int((s1.n_accepted + s1.n_rejected).item())}))
+        return
 
     if args.mode == "traffic":
         # A device copy of exactly 1 GiB calibrates FETCH_SIZE / WRITE_SIZE.
