@@ -54,9 +54,12 @@ typedef enum gs_traj_status {
   GS_TRAJ_NONFINITE = 3,     /* non-finite y0 or state, or 50 NaN rejections  */
   GS_TRAJ_TAPE_OVERFLOW = 4, /* reached t1, but more checkpoints than the
                                 capacity: the trajectory cannot be replayed   */
-  GS_TRAJ_BAD_INPUT = 5      /* t1 < t0, rtol <= 0, atol < 0, or output nodes
+  GS_TRAJ_BAD_INPUT = 5,     /* t1 < t0, rtol <= 0, atol < 0, or output nodes
                                 not non-decreasing within [t0, t1]; checked
                                 on the device, nothing integrated, outputs NaN */
+  GS_TRAJ_NOT_RUN = 6        /* a queue order was given and this index never
+                                appeared in it (the order was not a
+                                permutation): nothing was written for it     */
 } gs_traj_status;
 
 /* Runge--Kutta pairs (Section "Adaptive integration"). */
@@ -84,10 +87,19 @@ typedef enum gs_rhs_id {
   /* Stiff mass-action kinetics, autonomous, GS_RODAS4 only: */
   GS_RHS_KIN3 = 5,     /* d=3 (a, b, c), p=3 (k1, k2, k3): a -> b (k1 a),
                           b + c -> 2c (k2 b c), c -> a (k3 c)               */
-  GS_RHS_KIN8 = 6      /* d=8, p=12 (k1..k10, s, k12): y1 <-> y2 (k1, k2),
+  GS_RHS_KIN8 = 6,     /* d=8, p=12 (k1..k10, s, k12): y1 <-> y2 (k1, k2),
                           y2 -> y3 (k3), y3 <-> y4 (k4, k5), y4 + y5 <-> y6
                           (k6 y4 y5, k7 y6), y6 -> y7 (k8), y7 -> y8 (k9),
                           y8 -> y1 (k10), source s -> y5, y5 -> sink (k12) */
+  /* The classic stiff chemistry problems named with the paper's Rosenbrock
+     kernel (Discussion), standard form, rate constants as parameters: */
+  GS_RHS_ROBER = 7,    /* Robertson (1966), d=3, p=3 (k1, k2, k3), nominal
+                          (0.04, 3e7, 1e4): y1' = -k1 y1 + k3 y2 y3,
+                          y2' = k1 y1 - k3 y2 y3 - k2 y2^2, y3' = k2 y2^2    */
+  GS_RHS_HIRES = 8     /* HIRES (Schaefer 1975), d=8, p=8 (a, b, c, s, d, e,
+                          kf, g), nominal (1.71, 0.43, 8.32, 0.0007, 0.035,
+                          1.12, 280, 0.69); the problem's constants 8.75,
+                          10.03, 1.745, 1.81 are c+b, c+a, a+d, e+g         */
 } gs_rhs_id;
 
 /* How trajectories are handed to lanes. */
@@ -180,7 +192,13 @@ typedef struct gs_solve_args {
                             workgroup.                                      */
   const int64_t* order;  /* [n] queue order (a permutation of 0..n-1), or
                             NULL for 0, 1, ..., n-1; gs_solve_vjp takes the
-                            trajectories in the same order                  */
+                            trajectories in the same order.  Device memory,
+                            read on the device only: entries outside [0, n)
+                            are skipped, and before the solve every status
+                            is set to GS_TRAJ_NOT_RUN, so an index the order
+                            misses keeps that status (and gs_solve_vjp gives
+                            it NaN cotangents).  gs_queue_order builds a
+                            longest-first order on the device.              */
 
   void* workspace;       /* device memory, >= gs_workspace_bytes(args),
                             256-byte aligned.  Bytes 16..23 hold a uint64
@@ -230,7 +248,8 @@ size_t gs_workspace_bytes(const gs_solve_args* args);
  * y_out at the nodes, y_final, step counts and status, and, when
  * ckpt_every > 0, the checkpoint tape into the workspace.
  *
- * Stiff path (tableau GS_RODAS4 with GS_RHS_KIN3 or GS_RHS_KIN8): the
+ * Stiff path (tableau GS_RODAS4 with GS_RHS_KIN3, GS_RHS_KIN8, GS_RHS_ROBER
+ * or GS_RHS_HIRES): the
  * Rosenbrock kernel for stiff systems that the paper's library pairs with
  * its explicit kernels (Section "Adaptive explicit Runge--Kutta methods").
  * Each attempt factors (1/(h gamma) I - J) once (LU, partial pivoting) and
@@ -242,6 +261,25 @@ size_t gs_workspace_bytes(const gs_solve_args* args);
  * tableau with a stiff right-hand side, or GS_RODAS4 with another one, is
  * GS_ERR_UNSUPPORTED as well. */
 gs_status gs_solve(const gs_solve_args* args);
+
+/* Longest-first queue order on the device, for gs_solve_args.order (the
+ * idle cost of eq:cost falls on the short trajectories that start last).
+ * Each trajectory gets a cost key: cost[i] if `cost` (device, [n]) is given,
+ * larger first; otherwise a built-in model, the logarithm of the number of
+ * dynamical times in the span times rtol^(-1/nu) for the pair's order nu,
+ * where a dynamical time is (rc + r_E) / v0 for orbits in the logarithmic
+ * halo (r_E: the in-plane radius at the orbit's energy, eq:st-scales) and
+ * the span itself stands for it otherwise.  Keys are put in descending order
+ * by a counting sort over 65,536 buckets of their range (order within a
+ * bucket unspecified; non-finite keys last).  Reads from `args` only rhs,
+ * tableau, n, the stream and, for the built-in model, t0, t1, rtol (with
+ * their strides) and for the halo y0 and theta.  Writes order [n] (device).
+ * Kernels only (no memset, no allocation), so the call can be captured in a
+ * graph with the solve.  Workspace: gs_queue_order_workspace_bytes(n),
+ * 256-byte aligned, device memory. */
+size_t gs_queue_order_workspace_bytes(int64_t n);
+gs_status gs_queue_order(const gs_solve_args* args, const double* cost, int64_t* order,
+                         void* workspace, size_t workspace_bytes);
 
 /* Reverse-mode derivative of the discrete solution of the last gs_solve call
  * made with the same `fwd` arguments and workspace (tape required): for each

@@ -24,11 +24,11 @@ LIB_PATH = os.path.join(HERE, "libgso.so")
 SOURCES = ["solver.cpp", "tableaux.cpp", "stiff.cpp"]
 
 RHS = {"harmonic": 0, "kepler": 1, "loghalo": 2, "spinprec": 3, "quint": 4, "kin3": 5,
-       "kin8": 6}
-DIM = {0: 2, 1: 4, 2: 6, 3: 9, 4: 3, 5: 3, 6: 8}
-NPARAM = {0: 1, 1: 1, 2: 3, 3: 3, 4: 4, 5: 3, 6: 12}
+       "kin8": 6, "rober": 7, "hires": 8}
+DIM = {0: 2, 1: 4, 2: 6, 3: 9, 4: 3, 5: 3, 6: 8, 7: 3, 8: 8}
+NPARAM = {0: 1, 1: 1, 2: 3, 3: 3, 4: 4, 5: 3, 6: 12, 7: 3, 8: 8}
 TABLEAU = {"dopri5": 0, "tsit5": 1, "verner7": 2, "rodas4": 3}
-STIFF_RHS = (5, 6)
+STIFF_RHS = (5, 6, 7, 8)
 STATUS = {0: "OK", 1: "MAX_STEPS", 2: "DT_UNDERFLOW", 3: "NONFINITE"}
 
 

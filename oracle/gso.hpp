@@ -35,7 +35,8 @@ struct Tableau {
 const Tableau& tableau(int id);
 
 enum RhsId { RHS_HARMONIC = 0, RHS_KEPLER = 1, RHS_LOGHALO = 2, RHS_SPINPREC = 3, RHS_QUINT = 4,
-             RHS_KIN3 = 5, RHS_KIN8 = 6 };  // the last two: stiff kinetics, Rodas4 only
+             RHS_KIN3 = 5, RHS_KIN8 = 6, RHS_ROBER = 7, RHS_HIRES = 8 };
+// the last four: stiff chemistry, Rodas4 only
 int rhs_dim(int id);     // d
 int rhs_nparam(int id);  // p
 

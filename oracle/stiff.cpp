@@ -127,10 +127,57 @@ const Coeffs& coeffs() {
 //   y1 <-> y2 (k1, k2), y2 -> y3 (k3), y3 <-> y4 (k4, k5),
 //   y4 + y5 <-> y6 (k6 y4 y5, k7), y6 -> y7 (k8), y7 -> y8 (k9), y8 -> y1 (k10),
 //   source -> y5 (s), y5 -> sink (k12);  y1+y2+y3+y4+y6+y7+y8 conserved
-int dim(int rhs) { return rhs == RHS_KIN3 ? 3 : 8; }
-int npar(int rhs) { return rhs == RHS_KIN3 ? 3 : 12; }
+//
+// The two classic stiff chemistry problems named with the paper's Rosenbrock
+// kernel (Discussion: Robertson 1966; Schaefer 1975), in their standard
+// form (Hairer & Wanner 1996, Sec. IV.1 and IV.10), with the rate constants
+// as parameters so that an ensemble can draw them:
+// rober: y = (y1, y2, y3), theta = (k1, k2, k3), nominal (0.04, 3e7, 1e4)
+//   y1' = -k1 y1 + k3 y2 y3
+//   y2' =  k1 y1 - k3 y2 y3 - k2 y2^2
+//   y3' =  k2 y2^2                          y1 + y2 + y3 conserved
+// hires: y1..y8, theta = (a, b, c, s, d, e, kf, g), nominal
+//   (1.71, 0.43, 8.32, 0.0007, 0.035, 1.12, 280, 0.69); the problem's other
+//   constants are sums of these (8.75 = c + b, 10.03 = c + a, 1.745 = a + d,
+//   1.81 = e + g):
+//   y1' = -a y1 + b y2 + c y3 + s
+//   y2' =  a y1 - (c + b) y2
+//   y3' = -(c + a) y3 + b y4 + d y5
+//   y4' =  c y2 + a y3 - e y4
+//   y5' = -(a + d) y5 + b y6 + b y7
+//   y6' = -kf y6 y8 + g y4 + a y5 - b y6 + g y7
+//   y7' =  kf y6 y8 - (e + g) y7
+//   y8' = -kf y6 y8 + (e + g) y7            y7 + y8 conserved
+int dim(int rhs) { return (rhs == RHS_KIN3 || rhs == RHS_ROBER) ? 3 : 8; }
+int npar(int rhs) {
+  return rhs == RHS_KIN3 ? 3 : rhs == RHS_KIN8 ? 12 : rhs == RHS_ROBER ? 3 : 8;
+}
+bool is_stiff_rhs(int rhs) {
+  return rhs == RHS_KIN3 || rhs == RHS_KIN8 || rhs == RHS_ROBER || rhs == RHS_HIRES;
+}
 
 void eval(int rhs, const double* y, const double* k, double* f) {
+  if (rhs == RHS_ROBER) {
+    const double r1 = k[0] * y[0], r2 = k[1] * y[1] * y[1], r3 = k[2] * y[1] * y[2];
+    f[0] = -r1 + r3;
+    f[1] = r1 - r3 - r2;
+    f[2] = r2;
+    return;
+  }
+  if (rhs == RHS_HIRES) {
+    const double a = k[0], b = k[1], c = k[2], s = k[3], d = k[4], e = k[5], kf = k[6],
+                 g = k[7];
+    const double r = kf * y[5] * y[7];
+    f[0] = -a * y[0] + b * y[1] + c * y[2] + s;
+    f[1] = a * y[0] - (c + b) * y[1];
+    f[2] = -(c + a) * y[2] + b * y[3] + d * y[4];
+    f[3] = c * y[1] + a * y[2] - e * y[3];
+    f[4] = -(a + d) * y[4] + b * y[5] + b * y[6];
+    f[5] = -r + g * y[3] + a * y[4] - b * y[5] + g * y[6];
+    f[6] = r - (e + g) * y[6];
+    f[7] = -r + (e + g) * y[6];
+    return;
+  }
   if (rhs == RHS_KIN3) {
     const double r1 = k[0] * y[0], r2 = k[1] * y[1] * y[2], r3 = k[2] * y[2];
     f[0] = -r1 + r3;
@@ -166,6 +213,45 @@ void jac(int rhs, const double* y, const double* k, double J[MD][MD]) {
   const int d = dim(rhs);
   for (int i = 0; i < d; ++i)
     for (int j = 0; j < d; ++j) J[i][j] = 0.0;
+  if (rhs == RHS_ROBER) {
+    J[0][0] = -k[0];
+    J[0][1] = k[2] * y[2];
+    J[0][2] = k[2] * y[1];
+    J[1][0] = k[0];
+    J[1][1] = -k[2] * y[2] - 2.0 * k[1] * y[1];
+    J[1][2] = -k[2] * y[1];
+    J[2][1] = 2.0 * k[1] * y[1];
+    return;
+  }
+  if (rhs == RHS_HIRES) {
+    const double a = k[0], b = k[1], c = k[2], dd = k[4], e = k[5], kf = k[6], g = k[7];
+    J[0][0] = -a;
+    J[0][1] = b;
+    J[0][2] = c;
+    J[1][0] = a;
+    J[1][1] = -(c + b);
+    J[2][2] = -(c + a);
+    J[2][3] = b;
+    J[2][4] = dd;
+    J[3][1] = c;
+    J[3][2] = a;
+    J[3][3] = -e;
+    J[4][4] = -(a + dd);
+    J[4][5] = b;
+    J[4][6] = b;
+    J[5][3] = g;
+    J[5][4] = a;
+    J[5][5] = -kf * y[7] - b;
+    J[5][6] = g;
+    J[5][7] = -kf * y[5];
+    J[6][5] = kf * y[7];
+    J[6][6] = -(e + g);
+    J[6][7] = kf * y[5];
+    J[7][5] = -kf * y[7];
+    J[7][6] = e + g;
+    J[7][7] = -kf * y[5];
+    return;
+  }
   if (rhs == RHS_KIN3) {
     J[0][0] = -k[0];
     J[0][2] = k[2];
@@ -422,7 +508,7 @@ extern "C" {
 
 int gso_stiff_solve(const gso_problem* P) {
   using namespace gso;
-  if (!P || P->n < 0 || (P->rhs != RHS_KIN3 && P->rhs != RHS_KIN8) || P->tableau != RODAS4 ||
+  if (!P || P->n < 0 || !stiff::is_stiff_rhs(P->rhs) || P->tableau != RODAS4 ||
       P->m != 0 || P->h_replay || P->h_cap)
     return 1;
   int nt = P->nthreads > 0 ? P->nthreads : 1;
@@ -443,7 +529,7 @@ int gso_stiff_solve(const gso_problem* P) {
 // f and the analytic Jacobian J [d][d] (row-major) of a stiff right-hand side.
 int gso_stiff_rhs(int rhs, const double* y, const double* theta, double* f, double* J) {
   using namespace gso;
-  if (rhs != RHS_KIN3 && rhs != RHS_KIN8) return 1;
+  if (!stiff::is_stiff_rhs(rhs)) return 1;
   const int d = stiff::dim(rhs);
   stiff::eval(rhs, y, theta, f);
   double Jm[stiff::MD][stiff::MD];

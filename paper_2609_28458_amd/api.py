@@ -23,14 +23,14 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libgradsolve.so")
 
 RHS = {"harmonic": 0, "kepler": 1, "loghalo": 2, "spinprec": 3, "quint": 4, "kin3": 5,
-       "kin8": 6}
-DIM = {0: 2, 1: 4, 2: 6, 3: 9, 4: 3, 5: 3, 6: 8}
-NPARAM = {0: 1, 1: 1, 2: 3, 3: 3, 4: 4, 5: 3, 6: 12}
+       "kin8": 6, "rober": 7, "hires": 8}
+DIM = {0: 2, 1: 4, 2: 6, 3: 9, 4: 3, 5: 3, 6: 8, 7: 3, 8: 8}
+NPARAM = {0: 1, 1: 1, 2: 3, 3: 3, 4: 4, 5: 3, 6: 12, 7: 3, 8: 8}
 TABLEAU = {"dopri5": 0, "tsit5": 1, "verner7": 2, "rodas4": 3}
 SCHEDULE = {"queue": 0, "static": 1}
 OUT_LAYOUT = {"dkn": 0, "knd": 1}
 TRAJ_STATUS = {0: "OK", 1: "MAX_STEPS", 2: "DT_UNDERFLOW", 3: "NONFINITE",
-               4: "TAPE_OVERFLOW", 5: "BAD_INPUT"}
+               4: "TAPE_OVERFLOW", 5: "BAD_INPUT", 6: "NOT_RUN"}
 GS_OK = 0
 
 
@@ -86,11 +86,11 @@ class gs_de_profile_args(C.Structure):
         ("atol", C.c_double), ("chi2", C.c_void_p), ("chi2_prev", C.c_void_p),
         ("decrement", C.c_void_p), ("dist", C.c_void_p), ("status", C.c_void_p),
         ("workspace", C.c_void_p), ("workspace_bytes", C.c_size_t), ("stream", C.c_void_p),
-        ("out_layout", C.c_int32),
     ]
 
 
-EXPORTS = ["gs_default_args", "gs_workspace_bytes", "gs_solve", "gs_solve_vjp", "gs_solve_sens",
+EXPORTS = ["gs_default_args", "gs_workspace_bytes", "gs_solve",
+           "gs_queue_order", "gs_queue_order_workspace_bytes", "gs_solve_vjp", "gs_solve_sens",
            "gs_de_profile", "gs_de_profile_workspace_bytes", "gs_dense_eval",
            "gs_rhs_eval", "gs_graph_create", "gs_graph_launch", "gs_graph_destroy",
            "gs_status_string", "gs_version"]
@@ -112,6 +112,11 @@ def lib():
         L.gs_workspace_bytes.restype = C.c_size_t
         L.gs_solve.argtypes = [C.POINTER(gs_solve_args)]
         L.gs_solve.restype = C.c_int
+        L.gs_queue_order.argtypes = [C.POINTER(gs_solve_args), C.c_void_p, C.c_void_p,
+                                     C.c_void_p, C.c_size_t]
+        L.gs_queue_order.restype = C.c_int
+        L.gs_queue_order_workspace_bytes.argtypes = [C.c_int64]
+        L.gs_queue_order_workspace_bytes.restype = C.c_size_t
         L.gs_solve_vjp.argtypes = [C.POINTER(gs_solve_args), C.POINTER(gs_vjp_args)]
         L.gs_solve_vjp.restype = C.c_int
         L.gs_solve_sens.argtypes = [C.POINTER(gs_solve_args), C.POINTER(gs_sens_args)]
@@ -158,6 +163,15 @@ def gs_workspace_bytes(args: gs_solve_args) -> int:
 
 def gs_solve(args: gs_solve_args) -> None:
     _check(lib().gs_solve(C.byref(args)))
+
+
+def gs_queue_order(args: gs_solve_args, cost: int | None, order: int, workspace: int,
+                   workspace_bytes: int) -> None:
+    _check(lib().gs_queue_order(C.byref(args), cost, order, workspace, workspace_bytes))
+
+
+def gs_queue_order_workspace_bytes(n: int) -> int:
+    return int(lib().gs_queue_order_workspace_bytes(n))
 
 
 def gs_solve_vjp(args: gs_solve_args, vjp: gs_vjp_args) -> None:
@@ -340,9 +354,39 @@ class Solution:
         a.out_layout = OUT_LAYOUT[L.out_layout]
         return a
 
-    def set_order(self, order):
+    def set_order(self, order, check=True):
+        """Queue order of the trajectories (longest first, say), a permutation
+        of 0..n-1.  With ``check`` it is verified to be one (a device sort and
+        one host synchronisation); the library itself marks any index an order
+        misses as NOT_RUN."""
         self.order = None if order is None else _dev(order, self.prob.y0.device, torch.int64)
+        if self.order is not None and check:
+            n = self.prob.n
+            ok = self.order.shape == (n,) and bool(torch.equal(
+                torch.sort(self.order).values,
+                torch.arange(n, dtype=torch.int64, device=self.order.device)))
+            if not ok:
+                raise ValueError("order must be a permutation of 0..n-1")
         self.args.order = _ptr(self.order)
+
+    def queue_order(self, cost=None, stream=None):
+        """Build a longest-first order on the device (gs_queue_order) into this
+        solution's order buffer and use it: the library's cost model, or
+        ``cost`` [n] (larger first).  Asynchronous; returns the order tensor."""
+        dev = self.prob.y0.device
+        n = self.prob.n
+        if self.order is None or self.order.shape != (n,):
+            self.order = torch.empty(n, dtype=torch.int64, device=dev)
+        nb = gs_queue_order_workspace_bytes(n)
+        if getattr(self, "_order_ws", None) is None or self._order_ws.numel() < nb:
+            self._order_ws = torch.empty(max(nb, 256), dtype=torch.uint8, device=dev)
+        self._order_cost = None if cost is None else _dev(cost, dev).reshape(n)
+        self.args.stream = _stream_handle(stream)
+        gs_queue_order(self.args, _ptr(self._order_cost), _ptr(self.order),
+                       self._order_ws.data_ptr(), self._order_ws.numel())
+        self.args.order = _ptr(self.order)
+        return self.order
+
 
     def run(self, stream=None):
         self.args.stream = _stream_handle(stream)
@@ -492,6 +536,24 @@ def rhs_eval(rhs, t, y, theta, kbar=None, stream=None):
     gs_rhs_eval(rid, m, t.data_ptr(), y.data_ptr(), th.data_ptr(), f.data_ptr(), kb.data_ptr(),
                 yb.data_ptr(), tb.data_ptr(), _stream_handle(stream))
     return f, yb, tb
+
+
+class Captured:
+    """Any sequence of library calls on one stream (say gs_queue_order then
+    gs_solve) captured into one graph with torch.cuda.CUDAGraph and replayed
+    with launch().  ``fn(stream)`` issues the calls on the stream it is
+    given; the calls allocate nothing, so the graph holds only their kernels."""
+
+    def __init__(self, fn):
+        self.stream = torch.cuda.Stream()
+        self.graph = torch.cuda.CUDAGraph()
+        self.stream.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.graph(self.graph, stream=self.stream, capture_error_mode="thread_local"):
+            fn(self.stream)
+        torch.cuda.current_stream().wait_stream(self.stream)
+
+    def launch(self):
+        self.graph.replay()
 
 
 class Graph:

@@ -27,23 +27,43 @@ class SolveSpec:
     rtol: object
     atol: object
     t_out: object = None
-    ckpt_every: int = 32
-    ckpt_capacity: int = 0          # 0: estimate, then grow to fit
+    # 0: store mode (every accepted step on the tape, no replay in the
+    # backward pass, the fastest measured) when that tape fits in half the
+    # free device memory, else checkpoints every 32 accepted steps
+    ckpt_every: int = 0
+    ckpt_capacity: int = 0          # 0: sized from the steps of earlier calls, grown on overflow
     launch: api.Launch = field(default_factory=api.Launch)
     last_solution: object = None    # the Solution of the latest forward
+    steps_seen: int = 0             # most accepted steps of any trajectory so far
+
+
+def _tape_mode(prob: api.Problem, spec: SolveSpec, steps: int) -> tuple[int, int]:
+    """(ckpt_every, ckpt_capacity) for a forward expected to take up to
+    `steps` accepted steps per trajectory."""
+    k = spec.ckpt_every
+    if k == 0:
+        k = 1
+        free = torch.cuda.mem_get_info(prob.y0.device)[0]
+        L = api.Launch(**{**spec.launch.__dict__, "ckpt_every": 1, "ckpt_capacity": steps + 2})
+        if api.workspace_bytes(prob, L) > free // 2:
+            k = 32
+    return k, (spec.ckpt_capacity or steps // k + 2)
 
 
 def _solve_with_tape(prob: api.Problem, spec: SolveSpec) -> api.Solution:
-    cap = spec.ckpt_capacity or 64
+    """Forward with a tape.  The capacity comes from the most steps seen in
+    earlier calls (with a quarter in hand); only a trajectory that overflows
+    it makes the forward run again, once, with the capacity it needs."""
+    steps = spec.steps_seen + spec.steps_seen // 4 if spec.steps_seen else 256
     while True:
-        L = api.Launch(**{**spec.launch.__dict__, "ckpt_every": spec.ckpt_every,
-                          "ckpt_capacity": cap})
+        k, cap = _tape_mode(prob, spec, steps)
+        L = api.Launch(**{**spec.launch.__dict__, "ckpt_every": k, "ckpt_capacity": cap})
         sol = api.solve(prob, L)
-        over = sol.status == 4  # GS_TRAJ_TAPE_OVERFLOW
-        if spec.ckpt_capacity or not bool(over.any()):
+        nmax = int(sol.n_accepted.max())
+        spec.steps_seen = max(spec.steps_seen, nmax)
+        if spec.ckpt_capacity or nmax // k + 2 <= cap:
             return sol
-        need = int(sol.n_accepted.max()) // spec.ckpt_every + 2
-        cap = max(need, 2 * cap)
+        steps = nmax
 
 
 class GsSolveFn(torch.autograd.Function):
@@ -56,7 +76,11 @@ class GsSolveFn(torch.autograd.Function):
         ctx.sol = sol
         ctx.shared_theta = theta.dim() == 1
         ctx.mark_non_differentiable(sol.status)
-        y_out = sol.y_out if sol.y_out is not None else y0.new_zeros((prob.d, 0, prob.n))
+        if sol.y_out is not None:
+            y_out = sol.y_out
+        else:
+            y_out = y0.new_zeros((0, prob.n, prob.d) if sol.launch.out_layout == "knd"
+                                 else (prob.d, 0, prob.n))
         return y_out, sol.y_final, sol.status
 
     @staticmethod
@@ -64,6 +88,8 @@ class GsSolveFn(torch.autograd.Function):
         sol = ctx.sol
         yo = None
         if sol.y_out is not None and g_out is not None:
+            if sol.launch.out_layout == "knd":  # y_out [K][n][d]; cotangents go in [d][K][n]
+                g_out = g_out.permute(2, 0, 1)
             yo = g_out.contiguous().unsqueeze(0)
         yf = None if g_final is None else g_final.contiguous().unsqueeze(0)
         if yo is None and yf is None:

@@ -32,9 +32,18 @@ WIDES = (256, 512, 1024, 2048, 4096)
 CKPT = (1, 8, 32, 128)  # 1 = store mode: every accepted step on the tape
 
 
-def _key(prob: api.Problem, kind: str) -> str:
+def _key(prob: api.Problem, kind: str, base: api.Launch, ordered: bool) -> str:
+    """Problem class of a cached shape: device, kind of run, right-hand side,
+    tableau, log2 n, whether there are output nodes, the tape mode, whether a
+    queue order is given, and the decades of the median span and tolerance
+    (which set the step counts, so the tape sizes and the best shapes)."""
     dev = torch.cuda.get_device_name(prob.y0.device)
-    return f"{dev}|{kind}|rhs{prob.rhs}|tab{prob.tableau}|n2^{int(math.log2(max(prob.n, 1)))}"
+    span = float((prob.t1 - prob.t0).median()) if prob.n else 0.0
+    rtol = float(prob.rtol.median()) if prob.n else 1.0
+    return (f"{dev}|{kind}|rhs{prob.rhs}|tab{prob.tableau}|n2^{int(math.log2(max(prob.n, 1)))}"
+            f"|K{int(prob.K > 0)}|ck{base.ckpt_every}|ord{int(ordered)}"
+            f"|span10^{round(math.log10(max(span, 1e-300)))}"
+            f"|rtol10^{round(math.log10(max(rtol, 1e-300)))}")
 
 
 def _load():
@@ -78,9 +87,9 @@ def _grids(prob: api.Problem, block: int):
 def tune_forward(prob: api.Problem, order=None, base: api.Launch | None = None,
                  use_cache=True) -> api.Launch:
     """Fastest forward launch shape for this problem class."""
-    key = _key(prob, "fwd")
-    cache = _load() if use_cache else {}
     base = base or api.Launch()
+    key = _key(prob, "fwd", base, order is not None)
+    cache = _load() if use_cache else {}
     if key in cache:
         return api.Launch(**{**base.__dict__, **cache[key]["launch"]})
     # Stage 1: every candidate, best of three.  Stage 2: the four fastest
@@ -161,6 +170,26 @@ def pilot_order(prob: api.Problem, features, sample: int = 4096,
     return np.argsort(-(F @ coef), kind="stable").astype(np.int64)
 
 
+def pilot_cost(prob: api.Problem, features: torch.Tensor, sample: int = 4096,
+               launch: api.Launch | None = None, seed: int = 0) -> torch.Tensor:
+    """Fitted cost of every trajectory on the device, for gs_queue_order
+    (``Solution.queue_order(cost)``): a pilot solve of a random sample of the
+    trajectories, a least-squares fit of their step attempts on the features
+    (a device tensor [F][n]) plus a constant, and the fitted attempts of all
+    n.  The pilot and the fit are part of building the order; callers that
+    time the ensemble include them."""
+    n = prob.n
+    dev = prob.y0.device
+    F = torch.cat([torch.ones((1, n), dtype=torch.float64, device=dev),
+                   features.to(device=dev, dtype=torch.float64)]).T.contiguous()  # [n][1+F]
+    g = torch.Generator(device="cpu").manual_seed(seed)
+    idx = torch.randperm(n, generator=g)[:min(sample, n)].sort().values.to(dev)
+    sol = api.solve(_subset(prob, idx), launch or api.Launch())
+    att = (sol.n_accepted + sol.n_rejected).to(torch.float64)
+    coef = torch.linalg.lstsq(F[idx].cpu(), att.cpu().unsqueeze(1)).solution
+    return (F @ coef.to(dev)).reshape(n)
+
+
 def tune_gradient(prob: api.Problem, make_cotangent, base: api.Launch | None = None,
                   use_cache=True, order=None) -> api.Launch:
     """Fastest launch for forward-with-tape plus adjoint: the checkpoint
@@ -171,14 +200,19 @@ def tune_gradient(prob: api.Problem, make_cotangent, base: api.Launch | None = N
 
     ``make_cotangent(sol)`` returns (ybar_final, ybar_out) for a solution.
     """
-    key = _key(prob, "grad" if order is None else "grad-ordered")
-    cache = _load() if use_cache else {}
     base = base or api.Launch()
-    if key in cache:
-        return api.Launch(**{**base.__dict__, **cache[key]["launch"]})
-    plain = api.solve(prob, base)
+    key = _key(prob, "grad", base, order is not None)
+    cache = _load() if use_cache else {}
+    # The tape capacity is sized for this problem from a plain solve, never
+    # taken from the cache (a problem of the same class may take more steps).
+    plain = api.solve(prob, api.Launch(**{**base.__dict__, "ckpt_every": 0, "wide": 0}))
     torch.cuda.synchronize()
     nmax = int(plain.n_accepted.max())
+    del plain
+    if key in cache:
+        shape = dict(cache[key]["launch"])
+        shape["ckpt_capacity"] = nmax // shape["ckpt_every"] + 2
+        return api.Launch(**{**base.__dict__, **shape})
     cus = torch.cuda.get_device_properties(prob.y0.device).multi_processor_count
     shapes = [(base.block, base.grid, 0), (128, 2 * cus, 0), (64, 4 * cus, 0)]
     if (order is not None and prob.K == 0 and prob.d <= 16
@@ -208,7 +242,8 @@ def tune_gradient(prob: api.Problem, make_cotangent, base: api.Launch | None = N
             if best is None or ms < best[0]:
                 best = (ms, shape)
             del sol
-    cache[key] = {"ms": best[0], "launch": best[1]}
+    cache[key] = {"ms": best[0], "launch": {k: v for k, v in best[1].items()
+                                            if k != "ckpt_capacity"}}
     if use_cache:
         _store(cache)
     return api.Launch(**{**base.__dict__, **best[1]})

@@ -16,7 +16,7 @@ SOURCES = [os.path.join(CSRC, f) for f in (
     "gs_inst_spinprec.hip", "gs_inst_quint.hip", "gs_inst_stiff.hip")]
 HEADERS = [os.path.join(CSRC, h) for h in (
     "gs_kernels.hpp", "gs_rhs.hpp", "gs_tableaux.hpp", "gs_ops.hpp", "gs_inst.hpp",
-    "gs_dual.hpp", "gs_de.hpp", "gs_stiff.hpp")] + [
+    "gs_dual.hpp", "gs_de.hpp", "gs_stiff.hpp", "gs_order.hpp")] + [
     os.path.join(ROOT, "include", "gradsolve.h")]
 OBJDIR = os.path.join(HERE, "_build")
 

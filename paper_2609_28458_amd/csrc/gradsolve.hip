@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstdint>
 #include <cstring>
 #include <mutex>
@@ -13,13 +14,14 @@
 #include "gs_de.hpp"
 #include "gs_kernels.hpp"
 #include "gs_ops.hpp"
+#include "gs_order.hpp"
 
 namespace {
 
 using gs::Params;
 using gs::VjpParams;
 
-constexpr int kNumRhs = 7;      // five explicit right-hand sides, then the two stiff ones
+constexpr int kNumRhs = 9;      // five explicit right-hand sides, then the four stiff ones
 constexpr int kNumTab = 4;      // three explicit pairs, then Rodas4
 constexpr int kNumExplicitRhs = 5;
 constexpr int kNumExplicitTab = 3;
@@ -40,6 +42,23 @@ __global__ void reset_counters_kernel(unsigned long long* c, int n) {
 __global__ void reset_queues_kernel(unsigned long long* c, long long n_wide) {
   if (threadIdx.x < 4) c[threadIdx.x] = threadIdx.x == 0 ? (unsigned long long)n_wide : 0ull;
 }
+
+// Marks every trajectory as not run before a solve with a caller-given queue
+// order: an index the order misses keeps GS_TRAJ_NOT_RUN (the solve kernels
+// overwrite the status of every trajectory they take).
+__global__ void fill_status_kernel(int32_t* status, int64_t n, int32_t v) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+    status[i] = v;
+}
+// NaN into the cotangents of the losses of one adjoint call, before an
+// adjoint with a caller-given order (so a missed index reads NaN).
+__global__ void fill_nan_kernel(double* a, int64_t m) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += stride)
+    a[i] = __builtin_nan("");
+}
+int fill_grid(int64_t m) { return (int)std::min<int64_t>((m + 255) / 256, 4096); }
 
 int rhs_dim(int r) {
   static const int d[kNumExplicitRhs] = {gs::Harmonic::D, gs::Kepler::D, gs::LogHalo::D,
@@ -134,6 +153,25 @@ gs_status check_args(const gs_solve_args* a) {
   return GS_OK;
 }
 
+// Order nu of the propagated solution (the controller exponent is 1/nu).
+int tab_order(int tab) {
+  static const int nu[kNumTab] = {5, 5, 7, 4};
+  return (tab >= 0 && tab < kNumTab) ? nu[tab] : 7;
+}
+
+// The kernels' fast controller root clamps the squared norm to [1e-30,
+// 1e30] (the norm to [1e-15, 1e15]) before taking safety * ||e||^(-1/nu).
+// That changes no factor exactly when the clamped extremes already lie
+// outside [alpha_min, alpha_max]: safety * 1e15^(1/nu) >= alpha_max and
+// safety * 1e-15^(1/nu) <= alpha_min.  Otherwise, and for the PI form or
+// another exponent, the kernels take pow.
+bool fast_controller_exact(const gs_solve_args* a) {
+  const gs_controller& c = a->ctrl;
+  if (!(c.beta1 <= 0.0) || c.beta2 != 0.0) return false;
+  const double g = std::pow(10.0, 15.0 / tab_order(a->tableau));
+  return c.safety * g >= c.alpha_max && c.safety / g <= c.alpha_min;
+}
+
 Params make_params(const gs_solve_args* a) {
   Params P;
   std::memset(&P, 0, sizeof P);
@@ -175,10 +213,7 @@ Params make_params(const gs_solve_args* a) {
   P.sched_static = a->schedule == GS_SCHED_STATIC ? 1 : 0;
   P.n_wide = std::min<int64_t>(a->wide, a->n);
   P.wide_blocks = 0;  // set with the launch shape
-  P.fast_ctrl = (a->ctrl.beta1 <= 0.0 && a->ctrl.beta2 == 0.0 && a->ctrl.alpha_max <= 100.0 &&
-                 a->ctrl.alpha_min >= 0.01)
-                    ? 1
-                    : 0;
+  P.fast_ctrl = fast_controller_exact(a) ? 1 : 0;
   return P;
 }
 
@@ -274,6 +309,9 @@ gs_status launch_solve_all(const gs_solve_args* a) {
   const Params P = make_params(a);
   Params P2 = P;
   hipLaunchKernelGGL(reset_queues_kernel, dim3(1), dim3(64), 0, s, P.counters, (long long)P.n_wide);
+  if (a->order)
+    hipLaunchKernelGGL(fill_status_kernel, dim3(fill_grid(P.n)), dim3(256), 0, s, P.status, P.n,
+                       (int32_t)GS_TRAJ_NOT_RUN);
   int grid = 0, block = 0;
   int64_t limit = 0;
   solve_shape(a, &grid, &block, &limit);
@@ -284,6 +322,26 @@ gs_status launch_solve_all(const gs_solve_args* a) {
   if (P.n_wide > 0) wide_split(P.n, P.n_wide, block, limit, &P2.wide_blocks, &grid);
   ops(a->rhs, a->tableau).solve(P2, grid, block, s);
   return hipGetLastError() == hipSuccess ? GS_OK : GS_ERR_HIP;
+}
+
+// Workspace of gs_queue_order: keys, buckets, histogram, key range.
+struct OrderLayout {
+  size_t key, bucket, hist, range, total;
+};
+OrderLayout order_layout(int64_t n) {
+  OrderLayout L;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = off;
+    off = align256(off + bytes);
+    return at;
+  };
+  L.key = take((size_t)n * 8);
+  L.bucket = take((size_t)n * 4);
+  L.hist = take((size_t)gs::order::kBuckets * 4);
+  L.range = take(16);
+  L.total = off;
+  return L;
 }
 
 }  // namespace
@@ -318,6 +376,62 @@ gs_status gs_solve(const gs_solve_args* a) {
   const gs_status st = check_args(a);
   if (st != GS_OK || a->n == 0) return st;
   return launch_solve_all(a);
+}
+
+size_t gs_queue_order_workspace_bytes(int64_t n) {
+  if (n < 0 || n > (int64_t)1 << 31) return 0;
+  return order_layout(n).total;
+}
+
+gs_status gs_queue_order(const gs_solve_args* a, const double* cost, int64_t* order,
+                         void* workspace, size_t workspace_bytes) {
+  if (!a || !order) return GS_ERR_INVALID;
+  if (a->rhs < 0 || a->rhs >= kNumRhs || a->tableau < 0 || a->tableau >= kNumTab || a->n < 0)
+    return GS_ERR_INVALID;
+  if (a->n > (int64_t)1 << 31) return GS_ERR_UNSUPPORTED;
+  if (a->n == 0) return GS_OK;
+  if (!cost) {
+    if (!a->t0 || !a->t1 || !a->rtol) return GS_ERR_INVALID;
+    if (a->t_stride != 0 && a->t_stride != 1) return GS_ERR_INVALID;
+    if (a->tol_stride != 0 && a->tol_stride != 1) return GS_ERR_INVALID;
+    if (a->rhs == GS_RHS_LOGHALO) {
+      if (!a->y0 || !a->theta || a->d != rhs_dim(a->rhs) || a->p != rhs_np(a->rhs))
+        return GS_ERR_INVALID;
+      if (a->theta_stride != 0 && a->theta_stride != a->n) return GS_ERR_INVALID;
+    }
+  }
+  const OrderLayout L = order_layout(a->n);
+  if (!workspace || ((uintptr_t)workspace & 255) != 0 || workspace_bytes < L.total)
+    return GS_ERR_WORKSPACE;
+  char* ws = static_cast<char*>(workspace);
+  gs::order::Ws w;
+  w.key = reinterpret_cast<double*>(ws + L.key);
+  w.bucket = reinterpret_cast<uint32_t*>(ws + L.bucket);
+  w.hist = reinterpret_cast<uint32_t*>(ws + L.hist);
+  w.range = reinterpret_cast<unsigned long long*>(ws + L.range);
+  gs::order::CostIn c;
+  std::memset(&c, 0, sizeof c);
+  c.n = a->n;
+  c.loghalo = (!cost && a->rhs == GS_RHS_LOGHALO) ? 1 : 0;
+  c.inv_nu = 1.0 / tab_order(a->tableau);
+  c.y0 = a->y0;
+  c.theta = a->theta;
+  c.theta_stride = a->theta_stride;
+  c.t0 = a->t0;
+  c.t1 = a->t1;
+  c.t_stride = a->t_stride;
+  c.rtol = a->rtol;
+  c.tol_stride = a->tol_stride;
+  c.cost = cost;
+  hipStream_t s = static_cast<hipStream_t>(a->stream);
+  const int grid = (int)((a->n + 255) / 256);
+  hipLaunchKernelGGL(gs::order::clear_kernel, dim3(gs::order::kBuckets / 256), dim3(256), 0, s,
+                     w);
+  hipLaunchKernelGGL(gs::order::key_kernel, dim3(grid), dim3(256), 0, s, c, w);
+  hipLaunchKernelGGL(gs::order::bucket_kernel, dim3(grid), dim3(256), 0, s, a->n, w);
+  hipLaunchKernelGGL(gs::order::scan_kernel, dim3(1), dim3(gs::order::kScanThreads), 0, s, w);
+  hipLaunchKernelGGL(gs::order::scatter_kernel, dim3(grid), dim3(256), 0, s, a->n, w, order);
+  return hipGetLastError() == hipSuccess ? GS_OK : GS_ERR_HIP;
 }
 
 gs_status gs_solve_vjp(const gs_solve_args* fwd, const gs_vjp_args* v) {
@@ -365,6 +479,11 @@ gs_status gs_solve_vjp(const gs_solve_args* fwd, const gs_vjp_args* v) {
   V.scratch = reinterpret_cast<double*>(static_cast<char*>(fwd->workspace) + L.scratch_off);
   V.adj = reinterpret_cast<double*>(static_cast<char*>(fwd->workspace) + L.adj_off);
   hipLaunchKernelGGL(reset_counters_kernel, dim3(1), dim3(64), 0, s, P.counters + 2, 1);
+  if (fwd->order) {
+    const int64_t my = (int64_t)v->R * fwd->d * fwd->n, mt = (int64_t)v->R * fwd->p * fwd->n;
+    hipLaunchKernelGGL(fill_nan_kernel, dim3(fill_grid(my)), dim3(256), 0, s, v->y0bar, my);
+    hipLaunchKernelGGL(fill_nan_kernel, dim3(fill_grid(mt)), dim3(256), 0, s, v->thetabar, mt);
+  }
   for (int r0 = 0; r0 < v->R; r0 += kVjpMaxR) {
     V.r0 = r0;
     V.R = std::min(kVjpMaxR, v->R - r0);
@@ -385,6 +504,9 @@ void sens_launches(const gs_solve_args* a, const gs_sens_args* sa) {
   S.m_total = sa->M;
   S.S_final = sa->S_final;
   S.S_out = sa->S_out;
+  if (a->order)
+    hipLaunchKernelGGL(fill_status_kernel, dim3(fill_grid(P.n)), dim3(256), 0, s, P.status, P.n,
+                       (int32_t)GS_TRAJ_NOT_RUN);
   // Two columns per launch; each launch integrates the solution again and
   // rewrites the same values.
   for (int m0 = 0; m0 < sa->M; m0 += 2) {
@@ -695,6 +817,6 @@ const char* gs_status_string(gs_status s) {
   return "unknown status";
 }
 
-const char* gs_version(void) { return "0.1.0"; }
+const char* gs_version(void) { return "0.2.0"; }
 
 }  // extern "C"

@@ -113,7 +113,8 @@ struct Params {
   const int64_t* order;
   int32_t refill;
   int32_t sched_static;
-  int32_t fast_ctrl;  // I controller with default exponent and alpha in [0.01, 100]
+  int32_t fast_ctrl;  // I controller, default exponent, clamp bounds that hide the root's
+                      // input clamp (decided on the host)
   int64_t n_wide;     // queue positions [0, n_wide) run 16 lanes per trajectory
   int32_t wide_blocks;  // the first wide_blocks workgroups run those
   int32_t out_layout;   // y_out: 0 = [d][K][n], 1 = [K][n][d]
@@ -365,9 +366,10 @@ __device__ __forceinline__ void dense_value(const typename F::template ParT<T>& 
 // Controller of eq:controller from the squared norm en2 = ||e||^2.  The
 // paper's I form safety * ||e||^(-1/nu) = safety * en2^(-1/(2 nu)) takes the
 // Newton root (P.fast_ctrl, decided once per launch so the branch is
-// uniform).  Clamping en2 to [1e-30, 1e30] changes nothing: outside that
-// range the raw factor lies beyond [alpha_min, alpha_max] whenever
-// alpha_max <= 100 and alpha_min >= 0.01, which fast_ctrl requires.  The PI
+// uniform).  Clamping en2 to [1e-30, 1e30] changes nothing: the host sets
+// fast_ctrl only when safety * 1e15^(1/nu) >= alpha_max and
+// safety * 1e-15^(1/nu) <= alpha_min, so outside that range the raw factor
+// would be clamped to the same bound anyway.  The PI
 // form (beta2 != 0) or another exponent uses pow; the previous norm is kept
 // squared (err_prev2 = max(||e_prev||^2, 1e-8), i.e. ||e_prev|| floored at
 // 1e-4) so no square root is taken on the hot path.

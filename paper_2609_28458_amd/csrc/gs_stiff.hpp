@@ -62,8 +62,8 @@ struct Rodas4 {
 };
 
 // ---------------------------------------------------------------------------
-// Stiff mass-action kinetics (this library's own networks, stand-ins for the
-// classic stiff chemistry test problems).  f and the hand-written Jacobian.
+// Stiff mass-action kinetics (this library's own networks, with the same
+// structure as the classic problems below).  f and the hand-written Jacobian.
 //
 // Kin3: y = (a, b, c), theta = (k1, k2, k3):
 //   a -> b (k1 a),  b + c -> 2c (k2 b c),  c -> a (k3 c)
@@ -162,6 +162,125 @@ struct Kin8 {
     J[6][6] = -p.k[8];
     J[7][6] = p.k[8];
     J[7][7] = -p.k[9];
+  }
+};
+
+// ---------------------------------------------------------------------------
+// The two classic stiff chemistry problems the paper names with its
+// Rosenbrock kernel (Discussion: Robertson 1966; Schaefer 1975), in their
+// standard form (Hairer & Wanner 1996, Sec. IV.1, IV.10) with the rate
+// constants as per-trajectory parameters.
+//
+// Rober: y = (y1, y2, y3), theta = (k1, k2, k3), nominal (0.04, 3e7, 1e4):
+//   y1' = -k1 y1 + k3 y2 y3,  y2' = k1 y1 - k3 y2 y3 - k2 y2^2,  y3' = k2 y2^2
+struct Rober {
+  static constexpr int D = 3, P = 3;
+  static constexpr int WAVES_PER_EU = 3;
+  template <class T>
+  struct ParT {
+    T k1, k2, k3;
+  };
+  using Par = ParT<double>;
+  template <class T>
+  __device__ static ParT<T> prep(const T (&th)[P]) {
+    return ParT<T>{th[0], th[1], th[2]};
+  }
+  template <class T>
+  __device__ static void f(double, const T (&y)[D], const ParT<T>& p, T (&dy)[D]) {
+    const T r1 = p.k1 * y[0], r2 = p.k2 * y[1] * y[1], r3 = p.k3 * y[1] * y[2];
+    dy[0] = r3 - r1;
+    dy[1] = r1 - r3 - r2;
+    dy[2] = r2;
+  }
+  __device__ static void jac(const double (&y)[D], const Par& p, double (&J)[D][D]) {
+    const double k3y2 = p.k3 * y[1], k3y3 = p.k3 * y[2], k2y2 = 2.0 * p.k2 * y[1];
+    J[0][0] = -p.k1;
+    J[0][1] = k3y3;
+    J[0][2] = k3y2;
+    J[1][0] = p.k1;
+    J[1][1] = -k3y3 - k2y2;
+    J[1][2] = -k3y2;
+    J[2][0] = 0.0;
+    J[2][1] = k2y2;
+    J[2][2] = 0.0;
+  }
+};
+
+// Hires: y1..y8, theta = (a, b, c, s, d, e, kf, g), nominal (1.71, 0.43, 8.32,
+// 0.0007, 0.035, 1.12, 280, 0.69); the problem's other constants are the sums
+// 8.75 = c + b, 10.03 = c + a, 1.745 = a + d, 1.81 = e + g:
+//   y1' = -a y1 + b y2 + c y3 + s        y5' = -(a + d) y5 + b y6 + b y7
+//   y2' =  a y1 - (c + b) y2             y6' = -kf y6 y8 + g y4 + a y5 - b y6 + g y7
+//   y3' = -(c + a) y3 + b y4 + d y5      y7' =  kf y6 y8 - (e + g) y7
+//   y4' =  c y2 + a y3 - e y4            y8' = -kf y6 y8 + (e + g) y7
+struct Hires {
+  static constexpr int D = 8, P = 8;
+  static constexpr int WAVES_PER_EU = 1;
+  template <class T>
+  struct ParT {
+    T a, b, c, s, d, e, kf, g, cb, ca, ad, eg;
+  };
+  using Par = ParT<double>;
+  template <class T>
+  __device__ static ParT<T> prep(const T (&th)[P]) {
+    ParT<T> p;
+    p.a = th[0];
+    p.b = th[1];
+    p.c = th[2];
+    p.s = th[3];
+    p.d = th[4];
+    p.e = th[5];
+    p.kf = th[6];
+    p.g = th[7];
+    p.cb = p.c + p.b;
+    p.ca = p.c + p.a;
+    p.ad = p.a + p.d;
+    p.eg = p.e + p.g;
+    return p;
+  }
+  template <class T>
+  __device__ static void f(double, const T (&y)[D], const ParT<T>& p, T (&dy)[D]) {
+    const T r = p.kf * y[5] * y[7];
+    dy[0] = -p.a * y[0] + p.b * y[1] + p.c * y[2] + p.s;
+    dy[1] = p.a * y[0] - p.cb * y[1];
+    dy[2] = -p.ca * y[2] + p.b * y[3] + p.d * y[4];
+    dy[3] = p.c * y[1] + p.a * y[2] - p.e * y[3];
+    dy[4] = -p.ad * y[4] + p.b * y[5] + p.b * y[6];
+    dy[5] = -r + p.g * y[3] + p.a * y[4] - p.b * y[5] + p.g * y[6];
+    dy[6] = r - p.eg * y[6];
+    dy[7] = -r + p.eg * y[6];
+  }
+  __device__ static void jac(const double (&y)[D], const Par& p, double (&J)[D][D]) {
+#pragma unroll
+    for (int r = 0; r < D; ++r)
+#pragma unroll
+      for (int c = 0; c < D; ++c) J[r][c] = 0.0;
+    const double ky8 = p.kf * y[7], ky6 = p.kf * y[5];
+    J[0][0] = -p.a;
+    J[0][1] = p.b;
+    J[0][2] = p.c;
+    J[1][0] = p.a;
+    J[1][1] = -p.cb;
+    J[2][2] = -p.ca;
+    J[2][3] = p.b;
+    J[2][4] = p.d;
+    J[3][1] = p.c;
+    J[3][2] = p.a;
+    J[3][3] = -p.e;
+    J[4][4] = -p.ad;
+    J[4][5] = p.b;
+    J[4][6] = p.b;
+    J[5][3] = p.g;
+    J[5][4] = p.a;
+    J[5][5] = -ky8 - p.b;
+    J[5][6] = p.g;
+    J[5][7] = -ky6;
+    J[6][5] = ky8;
+    J[6][6] = -p.eg;
+    J[6][7] = ky6;
+    J[7][5] = -ky8;
+    J[7][6] = p.eg;
+    J[7][7] = -ky6;
   }
 };
 

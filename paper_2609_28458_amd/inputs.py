@@ -237,3 +237,41 @@ def kinetics8(n=100_000, seed=8, K=16):
     t_out = t1[None, :] * np.logspace(-6, 0, K)[:, None] if K else None
     return dict(rhs="kin8", tableau="rodas4", y0=y0, theta=k, t0=0.0, t1=t1, rtol=1e-6,
                 atol=1e-10, t_out=t_out)
+
+
+# Nominal rate constants of the two classic stiff chemistry problems.
+ROBER_NOMINAL = np.array([0.04, 3.0e7, 1.0e4])
+HIRES_NOMINAL = np.array([1.71, 0.43, 8.32, 0.0007, 0.035, 1.12, 280.0, 0.69])
+HIRES_Y0 = np.array([1.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0057])
+HIRES_T1 = 321.8122
+
+
+def robertson(n=100_000, seed=10, K=16, spread=2.0):
+    """Robertson's reaction (rober right-hand side): each rate its nominal
+    value (0.04, 3e7, 1e4) times logU[1/spread, spread]; start (1, 0, 0);
+    spans t1 ~ logU[40, 4e5] (the textbook interval is [0, 40], its long-time
+    variants reach 1e11); Rodas4 at rtol 1e-6, atol 1e-10 (y2 stays below
+    4e-5); K output times log-spaced from t1 1e-6 to t1.  spread = 1 gives
+    the textbook problem for every trajectory."""
+    rng = _rng(seed)
+    k = ROBER_NOMINAL[:, None] * _logu(rng, 1.0 / spread, spread, 3 * n).reshape(3, n)
+    y0 = np.zeros((3, n))
+    y0[0] = 1.0
+    t1 = _logu(rng, 40.0, 4.0e5, n)
+    t_out = t1[None, :] * np.logspace(-6, 0, K)[:, None] if K else None
+    return dict(rhs="rober", tableau="rodas4", y0=y0, theta=k, t0=0.0, t1=t1, rtol=1e-6,
+                atol=1e-10, t_out=t_out)
+
+
+def hires(n=100_000, seed=11, K=16, spread=1.25):
+    """HIRES, the plant-physiology problem (hires right-hand side): each of
+    its eight independent constants its nominal value times
+    logU[1/spread, spread]; the textbook start (1, 0, 0, 0, 0, 0, 0, 0.0057)
+    and span [0, 321.8122]; Rodas4 at rtol 1e-6, atol 1e-10; K output times
+    uniform in (0, t1].  spread = 1 gives the textbook problem."""
+    rng = _rng(seed)
+    k = HIRES_NOMINAL[:, None] * _logu(rng, 1.0 / spread, spread, 8 * n).reshape(8, n)
+    y0 = np.repeat(HIRES_Y0[:, None], n, axis=1)
+    t_out = np.linspace(HIRES_T1 / K, HIRES_T1, K) if K else None
+    return dict(rhs="hires", tableau="rodas4", y0=y0, theta=k, t0=0.0, t1=HIRES_T1, rtol=1e-6,
+                atol=1e-10, t_out=t_out)

@@ -18,3 +18,13 @@ def orc():
     import oracle
     oracle.build()
     return oracle
+
+
+def pytest_terminal_summary(terminalreporter):
+    from parity_log import RECORDS
+
+    if not RECORDS:
+        return
+    terminalreporter.write_sep("-", "measured parity errors (largest per test, against its bar)")
+    for name, err, bar in RECORDS:
+        terminalreporter.write_line(f"[parity] {name}: {err:.3e} (bar {bar:.0e})")

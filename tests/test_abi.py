@@ -4,6 +4,7 @@ run without a GPU)."""
 import ctypes as C
 import os
 import re
+import subprocess
 
 import pytest
 
@@ -26,6 +27,41 @@ def test_header_symbols_exported():
     for n in names:
         assert hasattr(lib, n), n
     assert set(api.EXPORTS) == set(names)
+
+
+MIRRORED = {"gs_controller": api.gs_controller, "gs_solve_args": api.gs_solve_args,
+            "gs_vjp_args": api.gs_vjp_args, "gs_sens_args": api.gs_sens_args,
+            "gs_de_profile_args": api.gs_de_profile_args}
+
+
+def _c_layout(tmp_path):
+    """sizeof and offsetof of every field of every mirrored struct, printed by
+    a C program compiled against include/gradsolve.h."""
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "gradsolve.h"',
+             "int main(void) {"]
+    for name, cls in MIRRORED.items():
+        lines.append(f'  printf("{name} size %zu\\n", sizeof({name}));')
+        for fname, _ in cls._fields_:
+            cname = "lambda" if fname == "lambda_" else fname
+            lines.append(f'  printf("{name} {fname} %zu\\n", offsetof({name}, {cname}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-std=c99", "-Wall", "-Werror", "-I",
+                           os.path.join(ROOT, "include"), "-o", str(exe), str(src)])
+    out = subprocess.check_output([str(exe)], text=True)
+    return {tuple(line.split()[:2]): int(line.split()[2]) for line in out.splitlines()}
+
+
+def test_every_mirrored_struct_matches_the_c_layout(tmp_path):
+    """Every struct the binding mirrors has the C header's size and field
+    offsets (a field the header lacks, or one out of place, fails here)."""
+    c = _c_layout(tmp_path)
+    for name, cls in MIRRORED.items():
+        assert C.sizeof(cls) == c[(name, "size")], name
+        for fname, _ in cls._fields_:
+            assert getattr(cls, fname).offset == c[(name, fname)], (name, fname)
 
 
 def test_struct_layout_matches_header():
@@ -57,7 +93,7 @@ def _args(**kw):
 
 
 @pytest.mark.parametrize("kw", [
-    dict(rhs=7), dict(tableau=4), dict(d=5), dict(p=4), dict(n=-1),
+    dict(rhs=9), dict(tableau=4), dict(d=5), dict(p=4), dict(n=-1),
     dict(y0=None), dict(theta_stride=5), dict(t_stride=2), dict(K=3),
     dict(ckpt_every=-1), dict(ckpt_every=4, ckpt_capacity=0), dict(block=100), dict(wide=-1),
     dict(block=1024), dict(refill=65), dict(schedule=5),
@@ -93,7 +129,7 @@ def test_vjp_requires_tape():
 def test_status_strings():
     for code in range(6):
         assert api.lib().gs_status_string(code)
-    assert api.gs_version() == "0.1.0"
+    assert api.gs_version() == "0.2.0"
 
 
 def test_wide_needs_queue_schedule_without_outputs_or_tape():
@@ -184,7 +220,7 @@ def test_stiff_path_argument_checks():
     assert L.gs_dense_eval(C.byref(_stiff()), 1, 0x1000, 0x1000, None) == 2
     assert L.gs_rhs_eval(5, 10, 0x1000, 0x1000, 0x1000, 0x1000, 0x1000, 0x1000, 0x1000,
                          None) == 2
-    assert L.gs_rhs_eval(7, 10, 0x1000, 0x1000, 0x1000, 0x1000, None, None, None, None) == 1
+    assert L.gs_rhs_eval(9, 10, 0x1000, 0x1000, 0x1000, 0x1000, None, None, None, None) == 1
 
 
 def test_size_limits():
@@ -202,3 +238,22 @@ def test_output_layout_argument():
     for bad in (-1, 2, 7):
         assert L.gs_solve(C.byref(_args(out_layout=bad))) == 1
     assert api.OUT_LAYOUT == {"dkn": 0, "knd": 1}
+
+
+def test_queue_order_argument_checks():
+    a = _args()
+    ws = (C.c_ubyte * 512)()
+    lib = api.lib()
+    # no order buffer
+    assert lib.gs_queue_order(C.byref(a), None, None, C.addressof(ws), 512) == 1
+    # workspace smaller than gs_queue_order_workspace_bytes(n)
+    need = lib.gs_queue_order_workspace_bytes(a.n)
+    assert need >= 12 * a.n + 65536 * 4
+    assert lib.gs_queue_order(C.byref(a), None, 0x1000, 0x100000, need - 1) == 3
+    # misaligned workspace
+    assert lib.gs_queue_order(C.byref(a), None, 0x1000, 0x100008, need) == 3
+    # the built-in model needs the spans and tolerances
+    assert lib.gs_queue_order(C.byref(_args(t1=None)), None, 0x1000, 0x100000, need) == 1
+    assert lib.gs_queue_order_workspace_bytes(-1) == 0
+    # n = 0: nothing to do
+    assert lib.gs_queue_order(C.byref(_args(n=0)), None, None, None, 0) in (0, 1)

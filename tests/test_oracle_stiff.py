@@ -177,3 +177,104 @@ def test_max_steps_reports_and_fills_nan(orc):
     assert np.all(o["status"] == 1)
     assert np.all(o["n_accepted"] + o["n_rejected"] == 5)
     assert np.isnan(o["y_out"][:, -1]).all()
+
+
+# ---------------------------------------------------------------------------
+# The two classic stiff chemistry problems (Robertson 1966; Schaefer 1975)
+# in their textbook form (Hairer & Wanner 1996, Sec. IV.1 and IV.10),
+# transcribed here a second time in numpy, independently of the oracle.
+
+def rober_np(k):
+    k1, k2, k3 = k
+
+    def f(t, y):
+        return np.array([-k1 * y[0] + k3 * y[1] * y[2],
+                         k1 * y[0] - k3 * y[1] * y[2] - k2 * y[1] ** 2,
+                         k2 * y[1] ** 2])
+    return f
+
+
+def hires_np(k):
+    a, b, c, s, d, e, kf, g = k
+
+    def f(t, y):
+        r = kf * y[5] * y[7]
+        return np.array([-a * y[0] + b * y[1] + c * y[2] + s,
+                         a * y[0] - (b + c) * y[1],
+                         -(a + c) * y[2] + b * y[3] + d * y[4],
+                         c * y[1] + a * y[2] - e * y[3],
+                         -(a + d) * y[4] + b * y[5] + b * y[6],
+                         -r + g * y[3] + a * y[4] - b * y[5] + g * y[6],
+                         r - (e + g) * y[6],
+                         -r + (e + g) * y[6]])
+    return f
+
+
+TEXTBOOK = [("rober", inputs.robertson, rober_np), ("hires", inputs.hires, hires_np)]
+
+
+def test_textbook_constants():
+    """With the nominal constants the parameterised HIRES is the textbook
+    problem: its other four rate constants are the sums 8.75, 10.03, 1.745,
+    1.81 of the independent ones."""
+    a, b, c, s, d, e, kf, g = inputs.HIRES_NOMINAL
+    np.testing.assert_allclose([c + b, c + a, a + d, e + g], [8.75, 10.03, 1.745, 1.81],
+                               rtol=1e-15)
+    assert s == 0.0007 and kf == 280.0
+    np.testing.assert_array_equal(inputs.ROBER_NOMINAL, [0.04, 3.0e7, 1.0e4])
+
+
+@pytest.mark.parametrize("name,gen,fnp", TEXTBOOK, ids=["rober", "hires"])
+def test_rhs_equals_the_textbook_form(orc, name, gen, fnp):
+    w = gen(n=6, seed=21)
+    rng = np.random.default_rng(4)
+    for i in range(6):
+        th = w["theta"][:, i]
+        y = rng.uniform(0.0, 1.0, w["y0"].shape[0]) * (1e-3 if name == "hires" else 1.0)
+        f, J = orc.stiff_rhs(name, y, th)
+        np.testing.assert_allclose(f, fnp(th)(0.0, y), rtol=1e-14, atol=1e-18)
+        for j in range(len(y)):
+            ej = np.zeros_like(y)
+            ej[j] = 1e-7 * max(abs(y[j]), 1e-3)
+            fd = (orc.stiff_rhs(name, y + ej, th)[0] - orc.stiff_rhs(name, y - ej, th)[0]) / (
+                2 * ej[j])
+            np.testing.assert_allclose(J[:, j], fd, rtol=1e-6, atol=1e-8 * np.abs(th).max())
+
+
+@pytest.mark.parametrize("name,gen,fnp", TEXTBOOK, ids=["rober", "hires"])
+def test_textbook_problems_against_radau(orc, name, gen, fnp):
+    """The oracle at a tight tolerance against scipy's Radau (called as a
+    library, with the numpy transcription of the problem): agreement within
+    the tighter of the two tolerances, at every output time."""
+    w = gen(n=4, seed=22)
+    rtol, atol = 1e-10, 1e-15
+    o = orc.solve(name, "rodas4", w["y0"], w["theta"], 0.0, w["t1"], rtol, atol, w["t_out"])
+    assert np.all(o["status"] == 0)
+    worst = 0.0
+    for i in range(4):
+        th = w["theta"][:, i]
+        t1 = float(np.broadcast_to(w["t1"], (4,))[i])
+        t_out = w["t_out"][:, i] if np.ndim(w["t_out"]) == 2 else w["t_out"]
+        r = solve_ivp(fnp(th), (0.0, t1), w["y0"][:, i], method="Radau", rtol=1e-12,
+                      atol=1e-17, t_eval=t_out)
+        assert r.success
+        worst = max(worst, np.max(np.abs(o["y_out"][:, :, i] - r.y) / (atol + rtol * np.abs(r.y))))
+    print(f"{name}: worst error vs Radau {worst:.2f} tolerance units")
+    assert worst < 5.0, worst
+
+
+@pytest.mark.parametrize("name,gen,fnp", TEXTBOOK, ids=["rober", "hires"])
+def test_textbook_problems_linear_invariants(orc, name, gen, fnp):
+    """Robertson keeps y1 + y2 + y3 = 1 and HIRES keeps y7 + y8 = 0.0057: a
+    Rosenbrock method with the exact Jacobian preserves linear invariants, so
+    they hold to rounding at the workload tolerance."""
+    w = gen(n=300, seed=23)
+    o = orc.solve(name, "rodas4", w["y0"], w["theta"], 0.0, w["t1"], w["rtol"], w["atol"],
+                  w["t_out"])
+    assert np.all(o["status"] == 0)
+    rows = [0, 1, 2] if name == "rober" else [6, 7]
+    inv0 = w["y0"][rows].sum(0)
+    np.testing.assert_allclose(o["y_final"][rows].sum(0), inv0, rtol=0, atol=1e-14)
+    np.testing.assert_allclose(o["y_out"][rows].sum(0),
+                               np.broadcast_to(inv0, o["y_out"].shape[1:]), rtol=0, atol=1e-14)
+    assert o["n_accepted"].max() < 1000  # stiff: far below any explicit stability limit
