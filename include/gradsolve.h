@@ -241,7 +241,9 @@ void gs_default_args(gs_solve_args* args);
  * checkpoint mode) and, with a tape, the adjoint's per-lane buffers for
  * min(n rounded up to 256, 131072) lanes: the running cotangents (d + p
  * doubles) and, in checkpoint mode, the replay scratch (ckpt_every steps of
- * 2 + d doubles).  Returns 0 for an invalid `args`. */
+ * 2 + d doubles); for GS_VERNER7 with K > 0 also 2 K n doubles for the
+ * outputs' shortened steps, which gs_solve evaluates after the solve kernel
+ * (one thread per output).  Returns 0 for an invalid `args`. */
 size_t gs_workspace_bytes(const gs_solve_args* args);
 
 /* Integrate every trajectory from t0 to t1 (eq:rk .. eq:dense), writing

@@ -302,6 +302,7 @@ def workspace_bytes(prob: Problem, launch: Launch) -> int:
     a = gs_default_args()
     a.rhs, a.tableau, a.n, a.d, a.p = prob.rhs, prob.tableau, prob.n, prob.d, NPARAM[prob.rhs]
     a.ckpt_every, a.ckpt_capacity = launch.ckpt_every, launch.ckpt_capacity
+    a.K = prob.K
     return gs_workspace_bytes(a)
 
 

@@ -171,20 +171,27 @@ def pilot_order(prob: api.Problem, features, sample: int = 4096,
 
 
 def pilot_cost(prob: api.Problem, features: torch.Tensor, sample: int = 4096,
-               launch: api.Launch | None = None, seed: int = 0) -> torch.Tensor:
+               launch: api.Launch | None = None, seed: int = 0,
+               tol_scale: float = 1.0) -> torch.Tensor:
     """Fitted cost of every trajectory on the device, for gs_queue_order
     (``Solution.queue_order(cost)``): a pilot solve of a random sample of the
     trajectories, a least-squares fit of their step attempts on the features
     (a device tensor [F][n]) plus a constant, and the fitted attempts of all
-    n.  The pilot and the fit are part of building the order; callers that
-    time the ensemble include them."""
+    n.  ``tol_scale`` > 1 runs the pilot at looser tolerances (the ranking of
+    the costs, not their size, sets the order, and a pilot's time is that of
+    its longest trajectory).  The pilot and the fit are part of building the
+    order; callers that time the ensemble report them."""
     n = prob.n
     dev = prob.y0.device
     F = torch.cat([torch.ones((1, n), dtype=torch.float64, device=dev),
                    features.to(device=dev, dtype=torch.float64)]).T.contiguous()  # [n][1+F]
     g = torch.Generator(device="cpu").manual_seed(seed)
     idx = torch.randperm(n, generator=g)[:min(sample, n)].sort().values.to(dev)
-    sol = api.solve(_subset(prob, idx), launch or api.Launch())
+    sub = _subset(prob, idx)
+    sub.t_out = None  # output times do not change the steps
+    if tol_scale != 1.0:
+        sub.rtol, sub.atol = sub.rtol * tol_scale, sub.atol * tol_scale
+    sol = api.solve(sub, launch or api.Launch())
     att = (sol.n_accepted + sol.n_rejected).to(torch.float64)
     coef = torch.linalg.lstsq(F[idx].cpu(), att.cpu().unsqueeze(1)).solution
     return (F @ coef.to(dev)).reshape(n)

@@ -83,9 +83,16 @@ int tab_stages(int tab) {
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 struct Layout {
-  size_t tape_off, tape_bytes, scratch_off, scratch_bytes, adj_off, adj_bytes, total;
+  size_t tape_off, tape_bytes, scratch_off, scratch_bytes, adj_off, adj_bytes, pending_off,
+      pending_bytes, total;
   int64_t adj_lanes;
 };
+
+// Outputs of the plain solve that are deferred shortened steps (explicit
+// pairs without a dense polynomial, K > 0): pending [2][K][n] doubles.
+bool defers_outputs(const gs_solve_args* a) {
+  return a->tableau == GS_VERNER7 && a->K > 0 && a->rhs >= 0 && a->rhs < kNumExplicitRhs;
+}
 
 Layout layout_of(const gs_solve_args* a) {
   Layout L;
@@ -108,7 +115,9 @@ Layout layout_of(const gs_solve_args* a) {
   }
   L.scratch_off = align256(L.tape_off + L.tape_bytes);
   L.adj_off = align256(L.scratch_off + L.scratch_bytes);
-  L.total = L.adj_off + L.adj_bytes;
+  L.pending_off = align256(L.adj_off + L.adj_bytes);
+  L.pending_bytes = defers_outputs(a) ? (size_t)2 * (size_t)a->K * (size_t)a->n * 8 : 0;
+  L.total = L.pending_off + L.pending_bytes;
   return L;
 }
 
@@ -208,6 +217,7 @@ Params make_params(const gs_solve_args* a) {
   char* ws = static_cast<char*>(a->workspace);
   P.counters = reinterpret_cast<unsigned long long*>(ws);
   P.tape = a->ckpt_every > 0 ? reinterpret_cast<double*>(ws + L.tape_off) : nullptr;
+  P.pending = L.pending_bytes ? reinterpret_cast<double*>(ws + L.pending_off) : nullptr;
   P.order = a->order;
   P.refill = a->refill > 0 ? a->refill : 8;
   P.sched_static = a->schedule == GS_SCHED_STATIC ? 1 : 0;
@@ -321,6 +331,7 @@ gs_status launch_solve_all(const gs_solve_args* a) {
   }
   if (P.n_wide > 0) wide_split(P.n, P.n_wide, block, limit, &P2.wide_blocks, &grid);
   ops(a->rhs, a->tableau).solve(P2, grid, block, s);
+  if (P.pending) ops(a->rhs, a->tableau).short_steps(P, s);
   return hipGetLastError() == hipSuccess ? GS_OK : GS_ERR_HIP;
 }
 

@@ -87,12 +87,22 @@ void launch_sens(const gs::Params& P, const gs::SensParams& S, int M, int grid, 
 }
 
 template <class TB, class F>
+void launch_short_steps(const gs::Params& P, hipStream_t s) {
+  if constexpr (!TB::POLY_DENSE) {
+    const int64_t m = (int64_t)P.K * P.n;
+    hipLaunchKernelGGL((gs::short_step_kernel<TB, F>), dim3((unsigned)((m + 255) / 256)), dim3(256),
+                       0, s, P);
+  }
+}
+
+template <class TB, class F>
 Ops make_ops() {
   return Ops{{{reinterpret_cast<const void*>(&gs::solve_kernel<TB, F, false, false>),
                reinterpret_cast<const void*>(&gs::solve_kernel<TB, F, false, true>)},
               {reinterpret_cast<const void*>(&gs::solve_kernel<TB, F, true, false>),
                reinterpret_cast<const void*>(&gs::solve_kernel<TB, F, true, true>)}},
-             &launch_solve<TB, F>, &launch_vjp<TB, F>, &launch_dense<TB, F>, &launch_sens<TB, F>};
+             &launch_solve<TB, F>, &launch_vjp<TB, F>, &launch_dense<TB, F>, &launch_sens<TB, F>,
+             &launch_short_steps<TB, F>};
 }
 
 template <class F>

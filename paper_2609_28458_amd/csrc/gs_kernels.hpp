@@ -118,6 +118,8 @@ struct Params {
   int64_t n_wide;     // queue positions [0, n_wide) run 16 lanes per trajectory
   int32_t wide_blocks;  // the first wide_blocks workgroups run those
   int32_t out_layout;   // y_out: 0 = [d][K][n], 1 = [K][n][d]
+  double* pending;      // [2][K][n]: start time and length of deferred shortened
+                        // steps (pairs without a dense polynomial, K > 0)
 };
 
 struct VjpParams {
@@ -330,11 +332,16 @@ __device__ double initial_step(const Inputs<F>& in, const double (&y)[F::D],
 // committed.  Polynomial pairs use eq:dense rewritten about the end of the
 // step, y + h sum_j b_j(sigma) k_j = y+ - h sum_j (b_j - b_j(sigma)) k_j, so the
 // start state need not stay live; Verner 7 takes a shortened step of length
-// sigma h from (t, y_start) reusing k[0] = f(t, y_start).
+// sigma h from (t, y_start) reusing k[0] = f(t, y_start).  The shortened
+// step runs in the step's own stage array: it overwrites k[1..s-1] (which a
+// pair without FSAL no longer needs once the step is accepted: its next
+// first stage is evaluated afresh) and keeps k[0], so several outputs in one
+// step each start from the same k[0].  A second stage array for it would
+// double the lane's largest live set.
 template <class TB, class F, class T>
 __device__ __forceinline__ void dense_value(const typename F::template ParT<T>& par, double t,
                                             double h, double sigma, const T (&y_end)[F::D],
-                                            const T (&y_start)[F::D], const T (&k)[TB::S][F::D],
+                                            const T (&y_start)[F::D], T (&k)[TB::S][F::D],
                                             T (&out)[F::D]) {
   constexpr int S = TB::S, D = F::D;
   if constexpr (TB::POLY_DENSE) {
@@ -356,10 +363,8 @@ __device__ __forceinline__ void dense_value(const typename F::template ParT<T>& 
       out[c] = fma(-h, acc, y_end[c]);
     }
   } else {
-    T ks[S][D];
-#pragma unroll
-    for (int c = 0; c < D; ++c) ks[0][c] = k[0][c];
-    rk_stages<TB, F>(par, t, sigma * h, y_start, ks, out);
+    static_assert(!TB::FSAL, "shortened-step outputs reuse the stages of a pair without FSAL");
+    rk_stages<TB, F>(par, t, sigma * h, y_start, k, out);
   }
 }
 
@@ -420,7 +425,8 @@ struct Attempt {
 // branch around the state); only output nodes run under a branch:
 // `on_accept(s, t_start, h, y_start)` sees y = y+, t = t_new and the step's
 // stages k (k[0] still f(t_start, y_start)); y_start is only meaningful for
-// shortened-step pairs.
+// shortened-step pairs, whose outputs may overwrite k[1..s-1] (see
+// dense_value).
 template <class TB, class F, class T, class OnAccept>
 __device__ __forceinline__ Attempt attempt(const Params& P, Traj<TB, F, T>& s,
                                            OnAccept&& on_accept) {
@@ -979,6 +985,11 @@ __device__ __forceinline__ void forward_body(const Params& P, const SensParams& 
   constexpr bool SENS = !std::is_same<T, double>::value;
   constexpr int M = ad::width<T>::value;
   static_assert(!(SENS && TAPE), "sensitivity solves keep no tape");
+  // Outputs of a pair without a dense polynomial are shortened steps; the
+  // plain solve defers them to short_step_kernel (one thread per output,
+  // after the solve), so that their stages never widen the attempt loop's
+  // register allocation.  The host then supplies the pending array.
+  constexpr bool DEFER = NODES && !SENS && !TB::POLY_DENSE;
   Traj<TB, F, T> s;
   int64_t idx = -1;
   int32_t kp = 0;
@@ -987,8 +998,14 @@ __device__ __forceinline__ void forward_body(const Params& P, const SensParams& 
   bool queue_empty = P.sched_static != 0;  // wave-uniform
   const int lane = threadIdx.x & 63;
 
-  // Output node kk of the lane's trajectory: values, and tangents.
-  auto put_node = [&](int kk, const T (&v)[D]) {
+  // Output node kk of the lane's trajectory: values, and tangents.  With
+  // deferred shortened steps the values are the step's start state and
+  // pending [2][K][n] gets the step's start time and length (0: done).
+  auto put_node = [&](int kk, const T (&v)[D], double t_start = 0.0, double hs = 0.0) {
+    if constexpr (DEFER) {
+      P.pending[(int64_t)kk * P.n + idx] = t_start;
+      P.pending[((int64_t)P.K + kk) * P.n + idx] = hs;
+    }
 #pragma unroll
     for (int c = 0; c < D; ++c) {
       P.y_out[P.out_layout ? ((int64_t)kk * P.n + idx) * D + c
@@ -1123,7 +1140,7 @@ __device__ __forceinline__ void forward_body(const Params& P, const SensParams& 
           st = ST_MAX_STEPS;
         } else {
           const Attempt a = attempt<TB, F>(
-              P, s, [&](const Traj<TB, F, T>& sa, double t_old, double hh, const T (&ys)[D]) {
+              P, s, [&](Traj<TB, F, T>& sa, double t_old, double hh, const T (&ys)[D]) {
                 if constexpr (!NODES) return;
                 // the next output time sits in a register: memory is read only
                 // when an output is passed, not on every accepted step
@@ -1131,6 +1148,10 @@ __device__ __forceinline__ void forward_body(const Params& P, const SensParams& 
                   const double tq = t_next;
                   if (tq == sa.t) {
                     put_node(kp, sa.y);
+                  } else if constexpr (DEFER) {
+                    // the shortened step from (t_old, ys) runs later, in
+                    // short_step_kernel; here its start and length
+                    put_node(kp, ys, t_old, ((tq - t_old) / hh) * hh);
                   } else {
                     T out[D];
                     dense_value<TB, F>(sa.in.par, t_old, hh, (tq - t_old) / hh, sa.y, ys, sa.k,
@@ -1183,6 +1204,38 @@ __global__ void __launch_bounds__(256)
     }
   }
   forward_body<TB, F, double, NODES, TAPE>(P, SensParams{});
+}
+
+// The deferred outputs of a pair without a dense polynomial: output kk of
+// trajectory i is one step of the pair of length hs from the step start
+// (t_start, y_start) that the solve left in pending and y_out, with k[0] =
+// f(t_start, y_start) evaluated afresh (the value the solve's own step
+// started from, so the result is the shortened step of eq:dense bit for
+// bit).  One thread per output, over [K][n]; hs = 0 marks an output the
+// solve already wrote.
+template <class TB, class F>
+__global__ void __launch_bounds__(256) short_step_kernel(Params P) {
+  constexpr int D = F::D;
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= (int64_t)P.K * P.n) return;
+  const int64_t i = g % P.n;
+  const int64_t kk = g / P.n;
+  const double hs = P.pending[((int64_t)P.K + kk) * P.n + i];
+  if (hs == 0.0) return;
+  const double t_start = P.pending[kk * P.n + i];
+  auto at = [&](int c) -> double& {
+    return P.y_out[P.out_layout ? (kk * P.n + i) * D + c : ((int64_t)c * P.K + kk) * P.n + i];
+  };
+  Inputs<F> in;
+  double y0_unused[D];
+  load_inputs<F>(P, i, in, y0_unused);
+  double y[D], k[TB::S][D], out[D];
+#pragma unroll
+  for (int c = 0; c < D; ++c) y[c] = at(c);
+  F::f(t_start, y, in.par, k[0]);
+  rk_stages<TB, F>(in.par, t_start, hs, y, k, out);
+#pragma unroll
+  for (int c = 0; c < D; ++c) at(c) = out[c];
 }
 
 // Forward solve with M sensitivity columns in the same launch.
@@ -1742,7 +1795,7 @@ __global__ void __launch_bounds__(256) dense_kernel(Params P, int32_t Q, const d
       s.nrej = 0;
       for (int guard = 0; guard < 100000000 && !done; ++guard) {
         const Attempt a = attempt<TB, F>(
-            P, s, [&](const Traj<TB, F>& sb, double t_old, double hh, const double (&ys)[D]) {
+            P, s, [&](Traj<TB, F>& sb, double t_old, double hh, const double (&ys)[D]) {
               if (tq <= sb.t) {
                 if (tq == sb.t) {
 #pragma unroll

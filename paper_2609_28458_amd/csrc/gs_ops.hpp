@@ -23,6 +23,8 @@ struct Ops {
   // Sensitivity solve with M (1 or 2) columns; grid <= 0 writes the blocks
   // per CU of the variant to *S.occupancy_out instead of launching.
   void (*sens)(const gs::Params&, const gs::SensParams&, int M, int grid, int block, hipStream_t);
+  // The deferred shortened-step outputs of a plain solve (P.pending set).
+  void (*short_steps)(const gs::Params&, hipStream_t);
 };
 
 // Fill row[GS_DOPRI5], row[GS_TSIT5], row[GS_VERNER7] for one right-hand side.
