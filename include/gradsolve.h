@@ -43,7 +43,9 @@ typedef enum gs_status {
   GS_ERR_UNSUPPORTED = 2, /* valid request the library does not implement    */
   GS_ERR_WORKSPACE = 3,   /* workspace missing or smaller than required      */
   GS_ERR_HIP = 4,         /* a HIP runtime call failed                       */
-  GS_ERR_NO_TAPE = 5      /* gradient requested but the solve kept no tape   */
+  GS_ERR_NO_TAPE = 5,     /* gradient requested but the solve kept no tape   */
+  GS_ERR_TOO_LARGE = 6    /* the request needs more scratch than the fixed
+                             static buffer of gs_solve_noalloc holds         */
 } gs_status;
 
 /* Per-trajectory outcome written to status[i]. */
@@ -263,6 +265,22 @@ size_t gs_workspace_bytes(const gs_solve_args* args);
  * tableau with a stiff right-hand side, or GS_RODAS4 with another one, is
  * GS_ERR_UNSUPPORTED as well. */
 gs_status gs_solve(const gs_solve_args* args);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): gs_solve
+ * without a caller workspace.  Exactly gs_solve's kernels and results; the
+ * work-queue counters live in a fixed static device buffer of the library
+ * (4 KiB per GPU, held until the process ends) instead of `workspace`, which
+ * is ignored.  Forward solves only: ckpt_every must be 0 (a tape would have
+ * to outlive the call for gs_solve_vjp, which reads the caller's workspace),
+ * else GS_ERR_UNSUPPORTED; a request needing more than the static buffer
+ * (gs_workspace_bytes above 4 KiB: GS_VERNER7 with 2 K n > 480, whose
+ * outputs' shortened steps keep 2 K n doubles) is GS_ERR_TOO_LARGE, returned
+ * before anything is launched.  Allocates nothing.  Every call on one GPU shares that
+ * buffer (the counters are reset by a kernel at the start of each call), so
+ * calls that overlap on one GPU -- on different streams, or from different
+ * threads without ordering -- race and must not be made. */
+gs_status gs_solve_noalloc(const gs_solve_args* args);
 
 /* Longest-first queue order on the device, for gs_solve_args.order (the
  * idle cost of eq:cost falls on the short trajectories that start last).

@@ -89,7 +89,7 @@ class gs_de_profile_args(C.Structure):
     ]
 
 
-EXPORTS = ["gs_default_args", "gs_workspace_bytes", "gs_solve",
+EXPORTS = ["gs_default_args", "gs_workspace_bytes", "gs_solve", "gs_solve_noalloc",
            "gs_queue_order", "gs_queue_order_workspace_bytes", "gs_solve_vjp", "gs_solve_sens",
            "gs_de_profile", "gs_de_profile_workspace_bytes", "gs_dense_eval",
            "gs_rhs_eval", "gs_graph_create", "gs_graph_launch", "gs_graph_destroy",
@@ -112,6 +112,8 @@ def lib():
         L.gs_workspace_bytes.restype = C.c_size_t
         L.gs_solve.argtypes = [C.POINTER(gs_solve_args)]
         L.gs_solve.restype = C.c_int
+        L.gs_solve_noalloc.argtypes = [C.POINTER(gs_solve_args)]
+        L.gs_solve_noalloc.restype = C.c_int
         L.gs_queue_order.argtypes = [C.POINTER(gs_solve_args), C.c_void_p, C.c_void_p,
                                      C.c_void_p, C.c_size_t]
         L.gs_queue_order.restype = C.c_int
@@ -163,6 +165,10 @@ def gs_workspace_bytes(args: gs_solve_args) -> int:
 
 def gs_solve(args: gs_solve_args) -> None:
     _check(lib().gs_solve(C.byref(args)))
+
+
+def gs_solve_noalloc(args: gs_solve_args) -> None:
+    _check(lib().gs_solve_noalloc(C.byref(args)))
 
 
 def gs_queue_order(args: gs_solve_args, cost: int | None, order: int, workspace: int,
@@ -388,6 +394,12 @@ class Solution:
         self.args.order = _ptr(self.order)
         return self.order
 
+    def run_noalloc(self, stream=None):
+        """The same solve through gs_solve_noalloc (no tape; the library's static
+        scratch instead of this solution's workspace)."""
+        self.args.stream = _stream_handle(stream)
+        gs_solve_noalloc(self.args)
+        return self
 
     def run(self, stream=None):
         self.args.stream = _stream_handle(stream)

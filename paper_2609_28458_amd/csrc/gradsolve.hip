@@ -335,6 +335,34 @@ gs_status launch_solve_all(const gs_solve_args* a) {
   return hipGetLastError() == hipSuccess ? GS_OK : GS_ERR_HIP;
 }
 
+// Fixed scratch of gs_solve_noalloc: the work-queue counters of a solve
+// without a tape (256 bytes used).  Each GPU the library runs on holds one
+// copy until the process ends; host code reaches it only through the device
+// address that hipGetSymbolAddress returns for the current device (the
+// array's own name is a host-side stand-in).
+constexpr size_t kStaticScratchBytes = 4096;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices];
+
+// Device address of `scratch` on the current device, looked up once per
+// device (with that device current) on its first use.
+gs_status static_scratch(void** out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return GS_ERR_HIP;
+  if (dev < 0 || dev >= kMaxDevices) return GS_ERR_UNSUPPORTED;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return GS_ERR_HIP;
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return GS_OK;
+}
+
 // Workspace of gs_queue_order: keys, buckets, histogram, key range.
 struct OrderLayout {
   size_t key, bucket, hist, range, total;
@@ -387,6 +415,23 @@ gs_status gs_solve(const gs_solve_args* a) {
   const gs_status st = check_args(a);
   if (st != GS_OK || a->n == 0) return st;
   return launch_solve_all(a);
+}
+
+gs_status gs_solve_noalloc(const gs_solve_args* a) {
+  if (!a) return GS_ERR_INVALID;
+  if (a->ckpt_every != 0) return GS_ERR_UNSUPPORTED;
+  gs_solve_args c = *a;
+  c.workspace = nullptr;
+  c.workspace_bytes = kStaticScratchBytes;
+  if (c.rhs >= 0 && c.rhs < kNumRhs && c.n >= 0 && layout_of(&c).total > kStaticScratchBytes)
+    return GS_ERR_TOO_LARGE;
+  void* p = nullptr;
+  const gs_status sp = static_scratch(&p);
+  if (sp != GS_OK) return sp;
+  c.workspace = p;
+  const gs_status st = check_args(&c);
+  if (st != GS_OK || c.n == 0) return st;
+  return launch_solve_all(&c);
 }
 
 size_t gs_queue_order_workspace_bytes(int64_t n) {
@@ -824,6 +869,7 @@ const char* gs_status_string(gs_status s) {
     case GS_ERR_WORKSPACE: return "workspace missing, misaligned or too small";
     case GS_ERR_HIP: return "HIP runtime error";
     case GS_ERR_NO_TAPE: return "no gradient tape (ckpt_every == 0)";
+    case GS_ERR_TOO_LARGE: return "request exceeds the fixed static scratch of gs_solve_noalloc";
   }
   return "unknown status";
 }

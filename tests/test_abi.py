@@ -257,3 +257,11 @@ def test_queue_order_argument_checks():
     assert lib.gs_queue_order_workspace_bytes(-1) == 0
     # n = 0: nothing to do
     assert lib.gs_queue_order(C.byref(_args(n=0)), None, None, None, 0) in (0, 1)
+
+
+def test_noalloc_argument_checks():
+    """The allocation-free solve rejects a tape before touching the device."""
+    lib = api.lib()
+    assert lib.gs_solve_noalloc(C.byref(_args(ckpt_every=1, ckpt_capacity=10))) == 2
+    assert lib.gs_solve_noalloc(None) == 1
+    assert lib.gs_status_string(6) == b"request exceeds the fixed static scratch of gs_solve_noalloc"

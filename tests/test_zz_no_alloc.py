@@ -1,0 +1,103 @@
+"""gs_solve_noalloc: the allocation-free variant of gs_solve (its queue
+counters in the library's static device scratch instead of a caller
+workspace) gives gs_solve's results bit for bit, on two calls in a row, the
+second on a smaller ensemble, through the C ABI."""
+import ctypes as C
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from paper_2609_28458_amd import api, inputs  # noqa: E402
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a GPU")
+    api.lib()
+
+
+def _pair(w, launch):
+    """The same problem solved by gs_solve and by gs_solve_noalloc (fresh
+    output buffers for each; the no-alloc call gets no workspace at all)."""
+    prob = api.make_problem(w["rhs"], w["tableau"], w["y0"], w["theta"], w["t0"], w["t1"],
+                            w["rtol"], w["atol"], w.get("t_out"))
+    ref = api.Solution(prob, launch)
+    ref.run()
+    out = api.Solution(prob, launch)
+    out.args.workspace = None
+    out.args.workspace_bytes = 0
+    out.args.stream = torch.cuda.current_stream().cuda_stream
+    rc = api.lib().gs_solve_noalloc(C.byref(out.args))
+    assert rc == 0, api.lib().gs_status_string(rc)
+    torch.cuda.synchronize()
+    return ref, out
+
+
+def _same(a, b):
+    for name in ("y_final", "n_accepted", "n_rejected", "status", "y_out"):
+        x, y = getattr(a, name), getattr(b, name)
+        if x is None:
+            assert y is None
+            continue
+        assert torch.equal(x, y), name
+
+
+def test_noalloc_matches_gs_solve_on_two_calls():
+    w1 = inputs.orbits_uneven(n=20_000, seed=91)
+    ref1, out1 = _pair(w1, api.Launch())
+    _same(ref1, out1)
+    assert bool((out1.status == 0).all())
+    # second call, smaller ensemble, outputs and a queue order: the counters
+    # the first call left behind are reset by the call itself
+    w2 = inputs.orbits_forward(n=700, seed=92)
+    prob2 = api.make_problem(w2["rhs"], w2["tableau"], w2["y0"], w2["theta"], w2["t0"],
+                             w2["t1"], w2["rtol"], w2["atol"], w2["t_out"])
+    order = torch.as_tensor(np.random.default_rng(5).permutation(700), device="cuda")
+    ref2 = api.Solution(prob2, api.Launch(block=128))
+    ref2.set_order(order)
+    ref2.run()
+    out2 = api.Solution(prob2, api.Launch(block=128))
+    out2.set_order(order)
+    out2.args.workspace = None
+    out2.args.workspace_bytes = 0
+    out2.args.stream = torch.cuda.current_stream().cuda_stream
+    assert api.lib().gs_solve_noalloc(C.byref(out2.args)) == 0
+    torch.cuda.synchronize()
+    _same(ref2, out2)
+    assert bool((out2.status == 0).all())
+
+
+def test_noalloc_rejects_a_tape_and_keeps_working():
+    w = inputs.orbits_forward(n=64, seed=93)
+    prob = api.make_problem(w["rhs"], w["tableau"], w["y0"], w["theta"], w["t0"], w["t1"],
+                            w["rtol"], w["atol"])
+    s = api.Solution(prob, api.Launch(ckpt_every=4, ckpt_capacity=400))
+    assert api.lib().gs_solve_noalloc(C.byref(s.args)) == 2   # GS_ERR_UNSUPPORTED
+    # 16-lane groups (queue schedule, final state only) share the counters too
+    ref, out = _pair({**w, "t_out": None}, api.Launch(wide=16))
+    _same(ref, out)
+
+
+def test_noalloc_size_limit_and_deferred_outputs():
+    """Verner 7 with outputs needs 2 K n doubles of scratch for its deferred
+    shortened steps: within the 4 KiB static buffer the results equal
+    gs_solve's; beyond it the call is refused with GS_ERR_TOO_LARGE before
+    anything runs."""
+    w = inputs.spin_precession(n=12, seed=94)
+    w.update(t0=100.0 ** -0.5, t_out=np.linspace(0.11, 0.3, 4))
+    ref, out = _pair(w, api.Launch())        # 256 + 2 * 4 * 12 * 8 bytes: fits
+    _same(ref, out)
+    big = inputs.spin_precession(n=64, seed=95)
+    big.update(t0=100.0 ** -0.5, t_out=np.linspace(0.11, 0.3, 8))
+    prob = api.make_problem(big["rhs"], big["tableau"], big["y0"], big["theta"], big["t0"],
+                            big["t1"], big["rtol"], big["atol"], big["t_out"])
+    s = api.Solution(prob, api.Launch())
+    s.status.fill_(-7)
+    torch.cuda.synchronize()
+    assert api.lib().gs_solve_noalloc(C.byref(s.args)) == 6   # GS_ERR_TOO_LARGE
+    torch.cuda.synchronize()
+    assert bool((s.status == -7).all())                       # nothing ran
