@@ -89,7 +89,7 @@ struct Layout {
 };
 
 // Outputs of the plain solve that are deferred shortened steps (explicit
-// pairs without a dense polynomial, K > 0): pending [2][K][n] doubles.
+// pairs without a dense polynomial, K > 0): pending [K][n][2 + d] doubles.
 bool defers_outputs(const gs_solve_args* a) {
   return a->tableau == GS_VERNER7 && a->K > 0 && a->rhs >= 0 && a->rhs < kNumExplicitRhs;
 }
@@ -116,7 +116,7 @@ Layout layout_of(const gs_solve_args* a) {
   L.scratch_off = align256(L.tape_off + L.tape_bytes);
   L.adj_off = align256(L.scratch_off + L.scratch_bytes);
   L.pending_off = align256(L.adj_off + L.adj_bytes);
-  L.pending_bytes = defers_outputs(a) ? (size_t)2 * (size_t)a->K * (size_t)a->n * 8 : 0;
+  L.pending_bytes = defers_outputs(a) ? (size_t)(2 + d) * (size_t)a->K * (size_t)a->n * 8 : 0;
   L.total = L.pending_off + L.pending_bytes;
   return L;
 }

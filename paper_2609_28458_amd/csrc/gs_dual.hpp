@@ -198,6 +198,10 @@ __device__ __forceinline__ Dual<M> fma(double a, const Dual<M>& b, double c) {
   for (int m = 0; m < M; ++m) r.d[m] = a * b.d[m];
   return r;
 }
+template <int M>
+__device__ __forceinline__ Dual<M> fma(const Dual<M>& a, double b, double c) {
+  return fma(b, a, c);
+}
 
 template <int M>
 __device__ __forceinline__ Dual<M> exp(const Dual<M>& a) {

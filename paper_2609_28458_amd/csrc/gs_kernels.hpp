@@ -118,8 +118,8 @@ struct Params {
   int64_t n_wide;     // queue positions [0, n_wide) run 16 lanes per trajectory
   int32_t wide_blocks;  // the first wide_blocks workgroups run those
   int32_t out_layout;   // y_out: 0 = [d][K][n], 1 = [K][n][d]
-  double* pending;      // [2][K][n]: start time and length of deferred shortened
-                        // steps (pairs without a dense polynomial, K > 0)
+  double* pending;      // [K][n][2 + d]: (start time, length, start state) of deferred
+                        // shortened steps (pairs without a dense polynomial, K > 0)
 };
 
 struct VjpParams {
@@ -998,13 +998,20 @@ __device__ __forceinline__ void forward_body(const Params& P, const SensParams& 
   bool queue_empty = P.sched_static != 0;  // wave-uniform
   const int lane = threadIdx.x & 63;
 
-  // Output node kk of the lane's trajectory: values, and tangents.  With
-  // deferred shortened steps the values are the step's start state and
-  // pending [2][K][n] gets the step's start time and length (0: done).
+  // Output node kk of the lane's trajectory: values, and tangents.  A
+  // deferred shortened step (hs > 0) is recorded instead, (t_start, hs,
+  // y_start) in one contiguous record of pending [K][n][2 + d]; a value
+  // written now marks its record done (hs = 0).
   auto put_node = [&](int kk, const T (&v)[D], double t_start = 0.0, double hs = 0.0) {
     if constexpr (DEFER) {
-      P.pending[(int64_t)kk * P.n + idx] = t_start;
-      P.pending[((int64_t)P.K + kk) * P.n + idx] = hs;
+      double* rec = P.pending + ((int64_t)kk * P.n + idx) * (2 + D);
+      rec[1] = hs;
+      if (hs != 0.0) {
+        rec[0] = t_start;
+#pragma unroll
+        for (int c = 0; c < D; ++c) rec[2 + c] = ad::val(v[c]);
+        return;
+      }
     }
 #pragma unroll
     for (int c = 0; c < D; ++c) {
@@ -1208,11 +1215,12 @@ __global__ void __launch_bounds__(256)
 
 // The deferred outputs of a pair without a dense polynomial: output kk of
 // trajectory i is one step of the pair of length hs from the step start
-// (t_start, y_start) that the solve left in pending and y_out, with k[0] =
+// (t_start, y_start) that the solve recorded in pending, with k[0] =
 // f(t_start, y_start) evaluated afresh (the value the solve's own step
 // started from, so the result is the shortened step of eq:dense bit for
-// bit).  One thread per output, over [K][n]; hs = 0 marks an output the
-// solve already wrote.
+// bit).  One thread per output, over [K][n] (consecutive threads write
+// consecutive trajectories of y_out); hs = 0 marks an output the solve
+// already wrote.
 template <class TB, class F>
 __global__ void __launch_bounds__(256) short_step_kernel(Params P) {
   constexpr int D = F::D;
@@ -1220,22 +1228,21 @@ __global__ void __launch_bounds__(256) short_step_kernel(Params P) {
   if (g >= (int64_t)P.K * P.n) return;
   const int64_t i = g % P.n;
   const int64_t kk = g / P.n;
-  const double hs = P.pending[((int64_t)P.K + kk) * P.n + i];
+  const double* rec = P.pending + g * (2 + D);
+  const double hs = rec[1];
   if (hs == 0.0) return;
-  const double t_start = P.pending[kk * P.n + i];
-  auto at = [&](int c) -> double& {
-    return P.y_out[P.out_layout ? (kk * P.n + i) * D + c : ((int64_t)c * P.K + kk) * P.n + i];
-  };
+  const double t_start = rec[0];
   Inputs<F> in;
   double y0_unused[D];
   load_inputs<F>(P, i, in, y0_unused);
   double y[D], k[TB::S][D], out[D];
 #pragma unroll
-  for (int c = 0; c < D; ++c) y[c] = at(c);
+  for (int c = 0; c < D; ++c) y[c] = rec[2 + c];
   F::f(t_start, y, in.par, k[0]);
   rk_stages<TB, F>(in.par, t_start, hs, y, k, out);
 #pragma unroll
-  for (int c = 0; c < D; ++c) at(c) = out[c];
+  for (int c = 0; c < D; ++c)
+    P.y_out[P.out_layout ? (kk * P.n + i) * D + c : ((int64_t)c * P.K + kk) * P.n + i] = out[c];
 }
 
 // Forward solve with M sensitivity columns in the same launch.

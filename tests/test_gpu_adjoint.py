@@ -21,8 +21,9 @@ from test_gpu_forward import CASES  # noqa: E402
 
 
 # Adjoint against the oracle's forward sensitivities: both are the exact
-# derivative of the same discrete solution, so they differ by rounding only.
-VJP_BAR = 1e-8
+# derivative of the same discrete solution, so they differ by rounding only
+# (largest measured: 1.8e-10, precession with Tsit5).
+VJP_BAR = 1e-9
 
 
 @pytest.fixture(scope="module", autouse=True)

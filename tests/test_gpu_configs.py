@@ -13,6 +13,7 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 from gpu_util import oracle_solve, rel_err, to_np  # noqa: E402
+from parity_log import record  # noqa: E402
 from paper_2609_28458_amd import api, inputs  # noqa: E402
 
 
@@ -29,12 +30,14 @@ def _prob(w, idx=None, **over):
                             w["rtol"], w["atol"], w.get("t_out"))
 
 
-def _parity(g, o, idx):
+def _parity(g, o, idx, what="config"):
     np.testing.assert_array_equal(g["n_accepted"][idx], o["n_accepted"])
     np.testing.assert_array_equal(g["n_rejected"][idx], o["n_rejected"])
-    assert np.max(rel_err(g["y_final"][:, idx], o["y_final"])) <= 1e-9
+    e = np.max(rel_err(g["y_final"][:, idx], o["y_final"]))
     if "y_out" in o:
-        assert np.max(rel_err(g["y_out"][:, :, idx], o["y_out"])) <= 1e-9
+        e = max(e, np.max(rel_err(g["y_out"][:, :, idx], o["y_out"])))
+    record(what, e, 1e-9)
+    assert e <= 1e-9, e
 
 
 def _p99(x):
@@ -111,17 +114,44 @@ def _angle_error(a, b):
 
 def test_spin_precession_full_size(orc):
     """10^6 binaries from r = 1000 to 10 with Verner 7 at 3.16e-9 and 32
-    outputs: parity on 100 sampled binaries.  From r = 1000 this tolerance
-    does not meet the 2e-7 rad budget (about 30 times more precession
-    cycles than from r = 100); the error is printed, and the budget is
-    checked at the loosest passing tolerance below."""
+    outputs: parity on 1,000 sampled binaries plus the 50 that took the most
+    attempts.  From r = 1000 this tolerance does not meet the 2e-7 rad
+    budget (about 30 times more precession cycles than from r = 100); the
+    error is printed, and the budget is checked at the loosest passing
+    tolerance below."""
     w = inputs.spin_precession()
     n = w["y0"].shape[1]
     g = to_np(api.solve(_prob(w)))
     assert np.all(g["status"] == 0)
-    idx = np.sort(np.random.default_rng(9).choice(n, 100, replace=False))
+    longest = np.argsort(-(g["n_accepted"] + g["n_rejected"]))[:50]
+    idx = np.unique(np.concatenate([np.random.default_rng(9).choice(n, 1000, replace=False),
+                                    longest]))
     o = oracle_solve(orc, w, idx)
-    _parity(g, o, idx)
+    np.testing.assert_array_equal(g["n_accepted"][idx], o["n_accepted"])
+    np.testing.assert_array_equal(g["n_rejected"][idx], o["n_rejected"])
+    # Over up to ~88,000 steps the precession amplifies rounding: changing the
+    # parameters by two ulps moves the oracle's own final directions by up to
+    # 1.4e-9 at identical step counts.  The GPU evaluates the right-hand side
+    # with fused multiply-adds where the oracle rounds every product, a
+    # difference of a few ulps per evaluation; the bar for each binary is
+    # 1e-9 or five times the oracle's own response to a change of the
+    # parameters of that size (1e-15 relative), whichever is larger.
+    th2 = w["theta"][:, idx] * (1.0 + 1e-15)
+    o2 = orc.solve(w["rhs"], w["tableau"], w["y0"][:, idx], th2, w["t0"], w["t1"], w["rtol"],
+                   w["atol"], w["t_out"])
+    self_d = np.maximum(np.abs(o2["y_final"] - o["y_final"]).max(axis=0),
+                        np.abs(o2["y_out"] - o["y_out"]).max(axis=(0, 1)))
+    bar = np.maximum(1e-9, 5.0 * self_d)
+    e = np.maximum(rel_err(g["y_final"][:, idx], o["y_final"]).max(axis=0),
+                   rel_err(g["y_out"][:, :, idx], o["y_out"]).max(axis=(0, 1)))
+    record("precession 10^6 at 3.16e-9, 1,050 sampled incl. the 50 longest: max error",
+           e.max(), 1e-9)
+    record("  same, error over the binary's own bar (<= 1)", (e / bar).max(), 1.0)
+    record("  same, binaries whose own rounding response exceeds 2e-10", (self_d > 2e-10).sum(),
+           len(idx))
+    assert np.all(e <= bar), (e.max(), (e / bar).max())
+    idx = idx[:100]
+    o = {k: v[..., :100] for k, v in o.items()}
     ref = orc.solve("spinprec", "verner7", w["y0"][:, idx], w["theta"][:, idx], w["t0"], w["t1"],
                     1e-13, 1e-13)
     eps = _angle_error(g["y_final"][:, idx], ref["y_final"])
@@ -201,7 +231,15 @@ def test_spin_precession_tilt_gradients(orc):
     ref = np.einsum("rjn,jcn->rcn", yb, o["S_final"])
     got = thb.cpu().numpy()[:, :, idx]
     scale = np.maximum(np.abs(ref).max(axis=1, keepdims=True), 1e-6)
-    assert np.max(np.abs(got - ref) / scale) < 1e-7
+    err = np.max(np.abs(got - ref) / scale)
+    # the gradient's own response to a rounding-level (1e-15 relative) change
+    # of the parameters (the same amplification of rounding as for the solution)
+    o2 = oracle_solve(orc, {**w, "theta": w["theta"] * (1.0 + 1e-15)}, idx, sens_cols=[9, 10, 11])
+    ref2 = np.einsum("rjn,jcn->rcn", yb, o2["S_final"])
+    self_d = np.max(np.abs(ref2 - ref) / scale)
+    record("tilt-angle gradients vs oracle FS (40 binaries from r = 1000)", err, 1e-7)
+    record("  the oracle's own response to a 1e-15 parameter change", self_d, 1e-7)
+    assert err < max(1e-7, 5.0 * self_d)
 
 
 @pytest.mark.parametrize("dense", [False, True])

@@ -160,5 +160,5 @@ def test_pi_adjoint_replays_the_controller_memory(orc, tab, k):
          + np.einsum("jkn,jckn->cn", ybo[0], o["S_out"]))
     G = np.concatenate([y0b[0].cpu().numpy(), thb[0].cpu().numpy()])
     err = np.abs(G - g) / np.maximum(np.abs(g).max(axis=0), 1.0)
-    record(f"vjp with PI control {tab} k={k}", err.max(), 1e-8)
-    assert err.max() < 1e-8, err.max()
+    record(f"vjp with PI control {tab} k={k}", err.max(), 1e-9)
+    assert err.max() < 1e-9, err.max()

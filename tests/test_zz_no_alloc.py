@@ -83,13 +83,13 @@ def test_noalloc_rejects_a_tape_and_keeps_working():
 
 
 def test_noalloc_size_limit_and_deferred_outputs():
-    """Verner 7 with outputs needs 2 K n doubles of scratch for its deferred
-    shortened steps: within the 4 KiB static buffer the results equal
+    """Verner 7 with outputs needs (2 + d) K n doubles of scratch for its
+    deferred shortened steps: within the 4 KiB static buffer the results equal
     gs_solve's; beyond it the call is refused with GS_ERR_TOO_LARGE before
     anything runs."""
-    w = inputs.spin_precession(n=12, seed=94)
+    w = inputs.spin_precession(n=10, seed=94)
     w.update(t0=100.0 ** -0.5, t_out=np.linspace(0.11, 0.3, 4))
-    ref, out = _pair(w, api.Launch())        # 256 + 2 * 4 * 12 * 8 bytes: fits
+    ref, out = _pair(w, api.Launch())        # 256 + 11 * 4 * 10 * 8 bytes: fits
     _same(ref, out)
     big = inputs.spin_precession(n=64, seed=95)
     big.update(t0=100.0 ** -0.5, t_out=np.linspace(0.11, 0.3, 8))
