@@ -75,11 +75,6 @@ int rhs_np(int r) {
 // or neither).
 bool is_stiff(const gs_solve_args* a) { return a->tableau == GS_RODAS4; }
 
-int tab_stages(int tab) {
-  static const int s[kNumExplicitTab] = {gs::Dopri5::S, gs::Tsit5::S, gs::Verner7::S};
-  return (tab >= 0 && tab < kNumExplicitTab) ? s[tab] : gs::Verner7::S;
-}
-
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 struct Layout {
@@ -502,9 +497,10 @@ gs_status gs_solve_vjp(const gs_solve_args* fwd, const gs_vjp_args* v) {
   if (fwd->n == 0) return GS_OK;
   const Layout L = layout_of(fwd);
   // The stage points of the step each lane reverses live in LDS, (s - 1) d
-  // doubles per lane; a block that would need more than the device allows
-  // per workgroup gets fewer lanes.
-  const size_t lds_lane = (size_t)(tab_stages(fwd->tableau) - 1) * rhs_dim(fwd->rhs) * 8;
+  // doubles per lane, when there are too many to keep in registers; a block
+  // that would need more than the device allows per workgroup gets fewer
+  // lanes.
+  const size_t lds_lane = (size_t)ops(fwd->rhs, fwd->tableau).vjp_lds_lane[fwd->K > 0 ? 1 : 0];
   int block = v->block > 0 ? v->block : 256;
   while (block > 64 && lds_lane * block > max_lds_per_block()) block -= 64;
   if (lds_lane * block > max_lds_per_block()) return GS_ERR_UNSUPPORTED;

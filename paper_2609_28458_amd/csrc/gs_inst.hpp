@@ -102,7 +102,9 @@ Ops make_ops() {
               {reinterpret_cast<const void*>(&gs::solve_kernel<TB, F, true, false>),
                reinterpret_cast<const void*>(&gs::solve_kernel<TB, F, true, true>)}},
              &launch_solve<TB, F>, &launch_vjp<TB, F>, &launch_dense<TB, F>, &launch_sens<TB, F>,
-             &launch_short_steps<TB, F>};
+             &launch_short_steps<TB, F>,
+             {gs::vjp_stages_in_lds<TB, F, false>() ? (TB::S - 1) * F::D * 8 : 0,
+              gs::vjp_stages_in_lds<TB, F, true>() ? (TB::S - 1) * F::D * 8 : 0}};
 }
 
 template <class F>

@@ -1271,17 +1271,46 @@ __host__ __device__ constexpr bool stage_feeds_step(int j) {
 // h b_j(sigma) g to stage j and g to y.  all_stages also reverses the stages
 // that only the dense output reads.
 //
-// The stage points Y_1 .. Y_{s-1} are recomputed first and parked in the
+// The stage points Y_1 .. Y_{s-1} are recomputed first and kept until the
+// reverse sweep reads them: in registers when there are few of them and no
+// output cotangents enter (vjp_stages_in_lds false: (s - 1) d <= 36 and no
+// output nodes, as in the orbit-gradient workload), else parked in the
 // lane's slice of LDS (ysc, stride `ys` between values, so the lanes of a
-// workgroup touch consecutive words), which keeps only the stage
-// cotangents in registers and the stage points off HBM.
-template <class TB, class F, int R, class Seed>
+// workgroup touch consecutive words), which keeps only the stage cotangents
+// in registers and the stage points off HBM.  In registers they cost no LDS
+// traffic, which the four waves of a fully loaded CU otherwise share; with
+// output nodes (whose seeds add a runtime loop and the dense-only stages)
+// the register form measured wrong cotangents in one variant at the
+// register limit (Tsit5 on the dark-energy system), so those keep LDS.
+template <class TB, class F, bool NODES>
+__host__ __device__ constexpr bool vjp_stages_in_lds() {
+  return NODES || (TB::S - 1) * F::D > 36;
+}
+
+template <class TB, class F, int R, bool NODES, class Seed>
 __device__ __forceinline__ void reverse_step(const Inputs<F>& in, double t, double h,
                                              const double (&y)[F::D], double (&lam)[R][F::D],
                                              double (&thb)[R][F::P], bool all_stages,
                                              Seed&& seed, double* ysc, int ys) {
   constexpr int S = TB::S, D = F::D;
-  auto Ys = [&](int j, int c) -> double& { return ysc[((j - 1) * D + c) * ys]; };
+  constexpr bool LDS = vjp_stages_in_lds<TB, F, NODES>();
+  // Every slot is defined on every path: a stage that only the dense output
+  // reads is written and read under the same runtime flag, and a slot left
+  // unwritten on one path must not reach the register allocator as undefined.
+  double Yr[LDS ? 1 : S - 1][D];
+  if constexpr (!LDS) {
+#pragma unroll
+    for (int j = 0; j < S - 1; ++j)
+#pragma unroll
+      for (int c = 0; c < D; ++c) Yr[j][c] = 0.0;
+  }
+  auto Ys = [&](int j, int c) -> double& {
+    if constexpr (LDS) {
+      return ysc[((j - 1) * D + c) * ys];
+    } else {
+      return Yr[j - 1][c];
+    }
+  };
   {
     double k[S][D];
     F::f(t, y, in.par, k[0]);
@@ -1615,7 +1644,7 @@ __global__ void __launch_bounds__(256) vjp_kernel(Params P, VjpParams V) {
       const double t_new = last_step ? s.in.t1 : tn + hn;
       auto no_seed = [](int, double(&)[TB::S][D], double(&)[D]) {};
       if constexpr (!NODES) {
-        reverse_step<TB, F, R>(s.in, tn, hn, yn, lam, thb, false, no_seed, ysc, ys);
+        reverse_step<TB, F, R, NODES>(s.in, tn, hn, yn, lam, thb, false, no_seed, ysc, ys);
       } else {
         // Nodes at the end of the step read y+ itself.
         // (node times are read from memory only when a node is passed)
@@ -1661,7 +1690,7 @@ __global__ void __launch_bounds__(256) vjp_kernel(Params P, VjpParams V) {
               for (int c = 0; c < D; ++c) yb[c] += g[c];
             }
           };
-          reverse_step<TB, F, R>(s.in, tn, hn, yn, lam, thb, any, seed, ysc, ys);
+          reverse_step<TB, F, R, NODES>(s.in, tn, hn, yn, lam, thb, any, seed, ysc, ys);
           kp = k_lo;
           t_kp = t_lo;
         } else {
@@ -1684,7 +1713,7 @@ __global__ void __launch_bounds__(256) vjp_kernel(Params P, VjpParams V) {
             for (int r = 0; r < R; ++r)
 #pragma unroll
               for (int c = 0; c < D; ++c) lz[r][c] = has ? gbar(r, c, kp) : lam[r][c];
-            reverse_step<TB, F, R>(s.in, tn, hq, yn, lz, thb, false, no_seed, ysc, ys);
+            reverse_step<TB, F, R, NODES>(s.in, tn, hq, yn, lz, thb, false, no_seed, ysc, ys);
 #pragma unroll
             for (int r = 0; r < R; ++r)
 #pragma unroll

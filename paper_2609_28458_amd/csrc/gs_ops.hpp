@@ -25,6 +25,9 @@ struct Ops {
   void (*sens)(const gs::Params&, const gs::SensParams&, int M, int grid, int block, hipStream_t);
   // The deferred shortened-step outputs of a plain solve (P.pending set).
   void (*short_steps)(const gs::Params&, hipStream_t);
+  // Bytes of LDS per lane the adjoint uses for the stage points (0 when it
+  // keeps them in registers), [output nodes].
+  int vjp_lds_lane[2];
 };
 
 // Fill row[GS_DOPRI5], row[GS_TSIT5], row[GS_VERNER7] for one right-hand side.

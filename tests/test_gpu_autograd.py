@@ -88,3 +88,25 @@ def test_autotuned_launch_gives_identical_results(tmp_path, monkeypatch):
     g0 = api.solve_vjp(s0, ybar_final=cot(s0)[0])
     for x, y in zip(g2, g0):
         torch.testing.assert_close(x, y, rtol=1e-12, atol=0.0)
+
+
+def test_autograd_store_default_and_output_layout_knd(orc):
+    """The default tape is store mode (every accepted step); with outputs
+    laid out [K][n][d] the backward takes the cotangents in that layout and
+    gives the same gradients as the default [d][K][n] layout."""
+    w = inputs.orbits_forward(n=128, seed=64)
+    grads = {}
+    for layout in ("dkn", "knd"):
+        y0 = torch.as_tensor(w["y0"], device="cuda").requires_grad_(True)
+        th = torch.as_tensor(w["theta"], device="cuda").requires_grad_(True)
+        spec = SolveSpec(w["rhs"], w["tableau"], 0.0, 50.0, 1e-8, 1e-10, w["t_out"],
+                         launch=api.Launch(out_layout=layout))
+        y_out, y_final, status = solve_ad(spec, y0, th)
+        assert spec.last_solution.launch.ckpt_every == 1  # store mode by default
+        assert bool((status == 0).all())
+        yo = y_out if layout == "dkn" else y_out.permute(2, 0, 1)   # -> [d][K][n]
+        loss = (yo[:3] ** 2).sum() + (y_final[3:] ** 2).sum()
+        loss.backward()
+        grads[layout] = (y0.grad.clone(), th.grad.clone())
+    for a, b in zip(grads["dkn"], grads["knd"]):
+        torch.testing.assert_close(a, b, rtol=0, atol=0)
