@@ -240,7 +240,9 @@ void gs_default_args(gs_solve_args* args);
 
 /* Bytes of workspace `args` needs: the work-queue counters, the tape
  * (n * ckpt_capacity records of 2 + d doubles in store mode, 3 + 2d in
- * checkpoint mode) and, with a tape, the adjoint's per-lane buffers for
+ * checkpoint mode; a trajectory's records sit in the slot of the queue
+ * position it was taken from, and n 32-bit slot numbers follow at the end
+ * of the workspace) and, with a tape, the adjoint's per-lane buffers for
  * min(n rounded up to 256, 131072) lanes: the running cotangents (d + p
  * doubles) and, in checkpoint mode, the replay scratch (ckpt_every steps of
  * 2 + d doubles); for GS_VERNER7 with K > 0 also (2 + d) K n doubles for

@@ -79,7 +79,7 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 struct Layout {
   size_t tape_off, tape_bytes, scratch_off, scratch_bytes, adj_off, adj_bytes, pending_off,
-      pending_bytes, total;
+      pending_bytes, slot_off, slot_bytes, total;
   int64_t adj_lanes;
 };
 
@@ -112,7 +112,11 @@ Layout layout_of(const gs_solve_args* a) {
   L.adj_off = align256(L.scratch_off + L.scratch_bytes);
   L.pending_off = align256(L.adj_off + L.adj_bytes);
   L.pending_bytes = defers_outputs(a) ? (size_t)(2 + d) * (size_t)a->K * (size_t)a->n * 8 : 0;
-  L.total = L.pending_off + L.pending_bytes;
+  // With a tape, each trajectory's tape slot (the queue position the
+  // forward took it from), read by the adjoint and dense queries.
+  L.slot_off = align256(L.pending_off + L.pending_bytes);
+  L.slot_bytes = a->ckpt_every > 0 ? (size_t)a->n * 4 : 0;
+  L.total = L.slot_off + L.slot_bytes;
   return L;
 }
 
@@ -213,6 +217,7 @@ Params make_params(const gs_solve_args* a) {
   P.counters = reinterpret_cast<unsigned long long*>(ws);
   P.tape = a->ckpt_every > 0 ? reinterpret_cast<double*>(ws + L.tape_off) : nullptr;
   P.pending = L.pending_bytes ? reinterpret_cast<double*>(ws + L.pending_off) : nullptr;
+  P.slot = L.slot_bytes ? reinterpret_cast<int32_t*>(ws + L.slot_off) : nullptr;
   P.order = a->order;
   P.refill = a->refill > 0 ? a->refill : 8;
   P.sched_static = a->schedule == GS_SCHED_STATIC ? 1 : 0;

@@ -108,7 +108,8 @@ struct Params {
   int32_t ckpt_every;
   int32_t ckpt_cap;
   int32_t store;                // ckpt_every == 1: every accepted step is on the tape
-  double* tape;                 // [n][ckpt_cap][record], record as in tape_record
+  double* tape;                 // [slot][ckpt_cap][record], record as in tape_record
+  int32_t* slot;                // [n]: tape slot of each trajectory (its queue position)
   unsigned long long* counters; // [0] forward queue, [1] adjoint queue, [2] replay mismatches
   const int64_t* order;
   int32_t refill;
@@ -508,16 +509,21 @@ __host__ __device__ constexpr int ckpt_record_len() { return 3 + 2 * F::D; }
 template <class F>
 __host__ __device__ constexpr int store_record_len() { return 2 + F::D; }
 
+// A trajectory's records sit in the tape slot of the queue position the
+// forward took it from (slot[i]), not at its index: the lanes of a wave take
+// neighbouring positions, so their records are neighbours in memory and the
+// translation of their addresses stays within few pages, where a caller's
+// order (longest first) would scatter them over the whole tape.
 template <class TB, class F>
-__device__ __forceinline__ double* tape_record(const Params& P, int64_t i, int c) {
+__device__ __forceinline__ double* tape_record(const Params& P, int64_t slot, int c) {
   const int rec = P.store ? store_record_len<F>() : ckpt_record_len<F>();
-  return P.tape + ((int64_t)i * P.ckpt_cap + c) * rec;
+  return P.tape + ((int64_t)slot * P.ckpt_cap + c) * rec;
 }
 
 template <class TB, class F>
-__device__ __forceinline__ void write_store_record(const Params& P, int64_t i, int n, double t,
+__device__ __forceinline__ void write_store_record(const Params& P, int64_t slot, int n, double t,
                                                    double h_in, const double (&y)[F::D]) {
-  double* r = P.tape + ((int64_t)i * P.ckpt_cap + n) * store_record_len<F>();
+  double* r = P.tape + ((int64_t)slot * P.ckpt_cap + n) * store_record_len<F>();
   r[0] = t;
   r[1] = h_in;
 #pragma unroll
@@ -525,9 +531,9 @@ __device__ __forceinline__ void write_store_record(const Params& P, int64_t i, i
 }
 
 template <class TB, class F>
-__device__ __forceinline__ void write_checkpoint(const Params& P, int64_t i, int c,
+__device__ __forceinline__ void write_checkpoint(const Params& P, int64_t slot, int c,
                                                  const Traj<TB, F>& s) {
-  double* r = tape_record<TB, F>(P, i, c);
+  double* r = tape_record<TB, F>(P, slot, c);
   r[0] = s.t;
   r[1] = s.h;
   r[2] = s.err_prev2;
@@ -539,9 +545,9 @@ __device__ __forceinline__ void write_checkpoint(const Params& P, int64_t i, int
 }
 
 template <class TB, class F>
-__device__ __forceinline__ void read_checkpoint(const Params& P, int64_t i, int c,
+__device__ __forceinline__ void read_checkpoint(const Params& P, int64_t slot, int c,
                                                 Traj<TB, F>& s) {
-  const double* r = tape_record<TB, F>(P, i, c);
+  const double* r = tape_record<TB, F>(P, slot, c);
   s.t = r[0];
   s.h = r[1];
   s.err_prev2 = r[2];
@@ -823,12 +829,12 @@ __device__ void solve_group(const Params& P) {
   GroupTraj<TB, F> s;
   GroupCoef<TB> cf;
   cf.load();
-  int64_t idx = -1;
+  int64_t idx = -1, ts = 0;  // trajectory and its tape slot
   bool live = false, overflow = false;
   bool queue_empty = false;
 
   auto put_record = [&](int n, double h_in) {
-    double* r = P.tape + ((int64_t)idx * P.ckpt_cap + n) * store_record_len<F>();
+    double* r = P.tape + ((int64_t)ts * P.ckpt_cap + n) * store_record_len<F>();
     if (c < D) r[2 + c] = s.y;
     if (c == 0) {
       r[0] = s.t;
@@ -844,10 +850,14 @@ __device__ void solve_group(const Params& P) {
     }
     live = false;
   };
-  auto start = [&](int64_t i) {
+  auto start = [&](int64_t i, int64_t slot) {
     idx = i;
+    ts = slot;
     live = true;
     overflow = false;
+    if constexpr (TAPE) {
+      if (c == 0) P.slot[i] = (int32_t)slot;
+    }
     s.nacc = s.nrej = s.nanrun = 0;
     s.err_prev2 = 1.0;
     double y0[D];
@@ -896,7 +906,7 @@ __device__ void solve_group(const Params& P) {
           const unsigned long long pos = base + __popcll(idle & below);
           if (pos < (unsigned long long)P.n_wide) {
             const int64_t id = P.order ? P.order[pos] : (int64_t)pos;
-            if (id >= 0 && id < P.n) start(id);
+            if (id >= 0 && id < P.n) start(id, (int64_t)pos);
           }
         }
       }
@@ -991,7 +1001,7 @@ __device__ __forceinline__ void forward_body(const Params& P, const SensParams& 
   // register allocation.  The host then supplies the pending array.
   constexpr bool DEFER = NODES && !SENS && !TB::POLY_DENSE;
   Traj<TB, F, T> s;
-  int64_t idx = -1;
+  int64_t idx = -1, ts = 0;  // trajectory and its tape slot
   int32_t kp = 0;
   double t_next = 0.0;  // time of output node kp, kept in a register (infinity after the last)
   bool live = false, overflow = false;
@@ -1050,9 +1060,12 @@ __device__ __forceinline__ void forward_body(const Params& P, const SensParams& 
     live = false;
   };
 
-  // Take trajectory i: load, validate, first evaluation, starting step.
-  auto start = [&](int64_t i) {
+  // Take trajectory i at tape slot `slot`: load, validate, first
+  // evaluation, starting step.
+  auto start = [&](int64_t i, int64_t slot) {
     idx = i;
+    ts = slot;
+    if constexpr (TAPE) P.slot[i] = (int32_t)slot;
     live = true;
     kp = 0;
     overflow = false;
@@ -1104,15 +1117,15 @@ __device__ __forceinline__ void forward_body(const Params& P, const SensParams& 
       if (P.ckpt_cap <= 0)
         overflow = true;
       else if (P.store)
-        write_store_record<TB, F>(P, i, 0, s.t, 0.0, s.y);
+        write_store_record<TB, F>(P, ts, 0, s.t, 0.0, s.y);
       else
-        write_checkpoint<TB, F>(P, i, 0, s);
+        write_checkpoint<TB, F>(P, ts, 0, s);
     }
   };
 
   if (P.sched_static) {
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (g < P.n) start(g);
+    if (g < P.n) start(g, g);
   }
 
   // Outer loop: bookkeeping (retire, refill).  Inner loop: step attempts of
@@ -1131,7 +1144,7 @@ __device__ __forceinline__ void forward_body(const Params& P, const SensParams& 
           const unsigned long long pos = base + __popcll(idle & lanemask_lt());
           if (pos < (unsigned long long)P.n) {
             const int64_t id = P.order ? P.order[pos] : (int64_t)pos;
-            if (id >= 0 && id < P.n) start(id);  // a bad permutation entry is skipped
+            if (id >= 0 && id < P.n) start(id, (int64_t)pos);  // a bad entry is skipped
           }
         }
       }
@@ -1174,7 +1187,7 @@ __device__ __forceinline__ void forward_body(const Params& P, const SensParams& 
             // Every accepted step, the last one included.
             if (a.accepted) {
               if (s.nacc < P.ckpt_cap)
-                write_store_record<TB, F>(P, idx, s.nacc, s.t, a.h_used, s.y);
+                write_store_record<TB, F>(P, ts, s.nacc, s.t, a.h_used, s.y);
               else
                 overflow = true;
             }
@@ -1184,7 +1197,7 @@ __device__ __forceinline__ void forward_body(const Params& P, const SensParams& 
               s.ck_left = P.ckpt_every;
               const int c = s.nacc / P.ckpt_every;
               if (c < P.ckpt_cap)
-                write_checkpoint<TB, F>(P, idx, c, s);
+                write_checkpoint<TB, F>(P, ts, c, s);
               else
                 overflow = true;
             }
@@ -1441,7 +1454,7 @@ __global__ void __launch_bounds__(256) vjp_kernel(Params P, VjpParams V) {
   auto LAM = [&](int r, int c) -> double& { return ast[(r * AREC + c) * 64]; };
   auto THB = [&](int r, int c) -> double& { return ast[(r * AREC + D + c) * 64]; };
 
-  int64_t idx = -1;
+  int64_t idx = -1, ts = 0;  // trajectory and its tape slot
   bool live = false, ok = false;
   bool queue_empty = false;  // wave-uniform
   int32_t N = 0, cseg = -1, kp = -1;
@@ -1476,6 +1489,7 @@ __global__ void __launch_bounds__(256) vjp_kernel(Params P, VjpParams V) {
     live = true;
     N = P.n_acc[i];
     ok = P.status[i] == ST_OK;
+    ts = ok ? (int64_t)P.slot[i] : 0;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
 #pragma unroll
@@ -1526,7 +1540,7 @@ __global__ void __launch_bounds__(256) vjp_kernel(Params P, VjpParams V) {
     if constexpr (!store) {
       // Replay the segment from its checkpoint (idle lanes: record 0 of
       // trajectory 0, likewise unused).
-      read_checkpoint<TB, F>(P, live ? idx : 0, live ? cseg : 0, s);
+      read_checkpoint<TB, F>(P, live ? ts : 0, live ? cseg : 0, s);
       s.nacc = cseg * kseg;
       s.nrej = 0;
       int j = 0;
@@ -1553,7 +1567,7 @@ __global__ void __launch_bounds__(256) vjp_kernel(Params P, VjpParams V) {
         // segment against the forward's final state.
         bool same = !lost;
         if (!lost && (cseg + 1) * kseg < N) {
-          const double* nxt = tape_record<TB, F>(P, idx, cseg + 1);
+          const double* nxt = tape_record<TB, F>(P, ts, cseg + 1);
 #pragma unroll
           for (int c = 0; c < D; ++c) same = same & (nxt[3 + c] == s.y[c]);
         } else if (!lost) {
@@ -1570,7 +1584,7 @@ __global__ void __launch_bounds__(256) vjp_kernel(Params P, VjpParams V) {
     // fetched before this step's arithmetic.
     const int fs = store ? 1 : 64;  // field stride of a record
     auto record = [&](int jj) -> const double* {
-      return store ? tape_record<TB, F>(P, idx, cseg * kseg + jj) : scr + (int64_t)jj * SREC * 64;
+      return store ? tape_record<TB, F>(P, ts, cseg * kseg + jj) : scr + (int64_t)jj * SREC * 64;
     };
     double nx_t = 0.0, nx_h = 0.0, nx_y[D];
     double h_carry = 0.0;  // store mode: h of the step about to be reversed
@@ -1587,7 +1601,7 @@ __global__ void __launch_bounds__(256) vjp_kernel(Params P, VjpParams V) {
       const double* rec = record(m - 1);
       if constexpr (store) {
         nxr.load(rec);
-        h_carry = tape_record<TB, F>(P, idx, cseg * kseg + m)[1];
+        h_carry = tape_record<TB, F>(P, ts, cseg * kseg + m)[1];
       } else {
         nx_t = rec[0];
         nx_h = rec[fs];
@@ -1758,6 +1772,7 @@ __global__ void __launch_bounds__(256) dense_kernel(Params P, int32_t Q, const d
   const int32_t st = P.status[i];
   const int32_t N = P.n_acc[i];
   const bool tape = P.ckpt_every > 0;
+  const int64_t ts = (tape && st == ST_OK) ? (int64_t)P.slot[i] : 0;  // tape slot
   const int nseg = tape ? min((N + P.ckpt_every - 1) / P.ckpt_every, P.ckpt_cap) : 0;
   for (int q = 0; q < Q; ++q) {
     const double tq = tq_all[(int64_t)q * P.n + i];
@@ -1777,13 +1792,13 @@ __global__ void __launch_bounds__(256) dense_kernel(Params P, int32_t Q, const d
       int lo = 0, hi = min(N, P.ckpt_cap - 1);
       while (lo < hi) {
         const int mid = (lo + hi + 1) / 2;
-        if (tape_record<TB, F>(P, i, mid)[0] < tq)
+        if (tape_record<TB, F>(P, ts, mid)[0] < tq)
           lo = mid;
         else
           hi = mid - 1;
       }
-      const double* rec = tape_record<TB, F>(P, i, lo);
-      const double* nxt = tape_record<TB, F>(P, i, lo + 1);
+      const double* rec = tape_record<TB, F>(P, ts, lo);
+      const double* nxt = tape_record<TB, F>(P, ts, lo + 1);
       if (lo >= N || lo + 1 >= P.ckpt_cap) {
 #pragma unroll
         for (int c = 0; c < D; ++c) out[c] = __builtin_nan("");
@@ -1812,12 +1827,12 @@ __global__ void __launch_bounds__(256) dense_kernel(Params P, int32_t Q, const d
         int lo = 0, hi = nseg - 1;
         while (lo < hi) {
           const int mid = (lo + hi + 1) / 2;
-          if (tape_record<TB, F>(P, i, mid)[0] < tq)
+          if (tape_record<TB, F>(P, ts, mid)[0] < tq)
             lo = mid;
           else
             hi = mid - 1;
         }
-        read_checkpoint<TB, F>(P, i, lo, s);
+        read_checkpoint<TB, F>(P, ts, lo, s);
       } else {
 #pragma unroll
         for (int c = 0; c < D; ++c) s.y[c] = y0[c];

@@ -108,12 +108,12 @@ def test_workspace_checks():
     a = _args(ckpt_every=8, ckpt_capacity=100)
     need = api.gs_workspace_bytes(a)
     # counters + tape (n * cap * (3 + 2d) doubles) + replay scratch (lanes * k * (2 + d))
-    # + running cotangents (lanes * (d + p), one loss per launch); every part is
-    # a multiple of 256 bytes
-    assert need == 256 + 1000 * 100 * 15 * 8 + 1024 * 8 * 8 * 8 + 1024 * 9 * 8
+    # + running cotangents (lanes * (d + p), one loss per launch), every part a
+    # multiple of 256 bytes, then the n 32-bit tape slots
+    assert need == 256 + 1000 * 100 * 15 * 8 + 1024 * 8 * 8 * 8 + 1024 * 9 * 8 + 1000 * 4
     store = api.gs_workspace_bytes(_args(ckpt_every=1, ckpt_capacity=100))
     # store mode: records of 2 + d doubles and no replay scratch
-    assert store == 256 + 1000 * 100 * 8 * 8 + 1024 * 9 * 8
+    assert store == 256 + 1000 * 100 * 8 * 8 + 1024 * 9 * 8 + 1000 * 4
     a.workspace_bytes = need - 1
     assert api.lib().gs_solve(C.byref(a)) == 3
     a = _args(workspace=0x100010)
