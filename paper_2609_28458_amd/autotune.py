@@ -26,8 +26,8 @@ CACHE = os.environ.get("GS_AUTOTUNE_CACHE",
 BLOCKS = (64, 128, 256)
 REFILLS = (1, 4, 8, 16, 64)
 # Trajectories at the head of the queue order run on 16-lane groups (wide):
-# tried on the best shapes when the call allows it (queue schedule, no
-# output nodes, no tape, at most 16 state components).
+# tried on the best shapes when the call allows it (queue schedule, no tape
+# or a store-mode tape, at most 16 state components, an explicit pair).
 WIDES = (256, 512, 1024, 2048, 4096)
 CKPT = (1, 8, 32, 128)  # 1 = store mode: every accepted step on the tape
 
@@ -106,7 +106,7 @@ def tune_forward(prob: api.Problem, order=None, base: api.Launch | None = None,
                     sol.set_order(order)
                 scored.append((_time(lambda: sol.run()), shape))
     scored.sort(key=lambda x: x[0])
-    if (order is not None and prob.K == 0 and base.ckpt_every == 0 and prob.d <= 16
+    if (order is not None and base.ckpt_every in (0, 1) and prob.d <= 16
             and prob.tableau != api.TABLEAU["rodas4"]):
         for _, shape0 in scored[:3]:
             for wide in WIDES:
@@ -222,8 +222,7 @@ def tune_gradient(prob: api.Problem, make_cotangent, base: api.Launch | None = N
         return api.Launch(**{**base.__dict__, **shape})
     cus = torch.cuda.get_device_properties(prob.y0.device).multi_processor_count
     shapes = [(base.block, base.grid, 0), (128, 2 * cus, 0), (64, 4 * cus, 0)]
-    if (order is not None and prob.K == 0 and prob.d <= 16
-            and prob.tableau != api.TABLEAU["rodas4"]):
+    if order is not None and prob.d <= 16 and prob.tableau != api.TABLEAU["rodas4"]:
         shapes.append((128, 2 * cus, 256))
     best = None
     free = torch.cuda.mem_get_info(prob.y0.device)[0]

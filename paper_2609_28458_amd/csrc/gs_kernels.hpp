@@ -743,9 +743,12 @@ struct GroupTraj {
 };
 
 // One attempt of a group: the single-lane attempt() component by component.
-template <class TB, class F>
+// on_accept(t_old, h, y_old) runs on acceptance with the new state in s and
+// the step's stages still in s.k, as in the single-lane attempt.
+template <class TB, class F, class OnAccept>
 __device__ __forceinline__ Attempt group_attempt(const Params& P, const GroupCoef<TB>& cf,
-                                                 GroupTraj<TB, F>& s, int c) {
+                                                 GroupTraj<TB, F>& s, int c,
+                                                 OnAccept&& on_accept) {
   constexpr int S = TB::S, D = F::D;
   Attempt a;
   a.t_start = s.t;
@@ -792,8 +795,10 @@ __device__ __forceinline__ Attempt group_attempt(const Params& P, const GroupCoe
   const double t_new = last ? s.in.t1 : s.t + hh;
   a.t_new = t_new;
   const bool fin = row_sum<D>(fma(yn, 0.0, 0.0)) == 0.0;
+  const double y_old = s.y;
   s.y = acc ? yn : s.y;
   s.t = acc ? t_new : s.t;
+  if (acc) on_accept(a.t_start, hh, y_old);
   if constexpr (TB::FSAL) {
     s.k[0] = acc ? s.k[S - 1] : s.k[0];
   } else {
@@ -813,6 +818,29 @@ __device__ __forceinline__ Attempt group_attempt(const Params& P, const GroupCoe
   return a;
 }
 
+// Component of the dense output (eq:dense) of a pair with a dense
+// polynomial, for the group lane that holds this component: the expression
+// and order of dense_value, so the value is that of one lane.
+template <class TB>
+__device__ __forceinline__ double group_dense(double h, double sigma, double y_end,
+                                              const double (&k)[TB::S]) {
+  constexpr int S = TB::S;
+  double w[S];
+  sfor<S>([&](auto J) {
+    constexpr int j = decltype(J)::value;
+    double acc = 0.0;
+    rfor<TB::DEG>([&](auto Q) {
+      constexpr int q = decltype(Q)::value;
+      acc = fma(acc, sigma, TB::Bs(j, q));
+    });
+    w[j] = TB::B(j) - acc * sigma;
+  });
+  double acc = 0.0;
+#pragma unroll
+  for (int j = 0; j < S; ++j) acc = fma(w[j], k[j], acc);
+  return fma(-h, acc, y_end);
+}
+
 // The group part of a forward launch: workgroups [0, wide_blocks) take the
 // queue positions [0, n_wide) (the head of the order, longest first when
 // the caller sorts by predicted cost), one per 16-lane group, from their own
@@ -820,9 +848,14 @@ __device__ __forceinline__ Attempt group_attempt(const Params& P, const GroupCoe
 // ballot sits where all lanes of the wave execute it.  TAPE: a store-mode
 // tape (every accepted step), written as one lane writes it: lane c of the
 // group stores component c of each record, lane 0 its time and step.
-template <class TB, class F, bool TAPE>
+// NODES: output nodes, written as one lane writes them (lane c component c):
+// exact hits and dense values of pairs with a dense polynomial directly,
+// and for the other pairs the deferred shortened step's record (lane 0 its
+// start time and length, lane c component c of its start state).
+template <class TB, class F, bool NODES, bool TAPE>
 __device__ void solve_group(const Params& P) {
   constexpr int D = F::D;
+  constexpr bool DEFER = NODES && !TB::POLY_DENSE;
   const int lane = threadIdx.x & 63;
   const int c = lane & (kGroup - 1);
   const int first = lane & ~(kGroup - 1);  // the group's lane 0
@@ -832,7 +865,23 @@ __device__ void solve_group(const Params& P) {
   int64_t idx = -1, ts = 0;  // trajectory and its tape slot
   bool live = false, overflow = false;
   bool queue_empty = false;
+  int kp = 0;                           // next output node
+  double t_next = __builtin_inf();      // its time, kept in a register
 
+  auto put_node = [&](int kk, double v, double t_start = 0.0, double hs = 0.0) {
+    if constexpr (DEFER) {
+      double* rec = P.pending + ((int64_t)kk * P.n + idx) * (2 + D);
+      if (c == 0) rec[1] = hs;
+      if (hs != 0.0) {
+        if (c == 0) rec[0] = t_start;
+        if (c < D) rec[2 + c] = v;
+        return;
+      }
+    }
+    if (c < D)
+      P.y_out[P.out_layout ? ((int64_t)kk * P.n + idx) * D + c
+                           : ((int64_t)c * P.K + kk) * P.n + idx] = v;
+  };
   auto put_record = [&](int n, double h_in) {
     double* r = P.tape + ((int64_t)ts * P.ckpt_cap + n) * store_record_len<F>();
     if (c < D) r[2 + c] = s.y;
@@ -842,6 +891,7 @@ __device__ void solve_group(const Params& P) {
     }
   };
   auto finish = [&](int32_t st) {
+    for (; NODES && kp < P.K; ++kp) put_node(kp, __builtin_nan(""));
     if (c < D) P.y_final[(int64_t)c * P.n + idx] = s.y;
     if (c == 0) {
       P.n_acc[idx] = s.nacc;
@@ -867,10 +917,17 @@ __device__ void solve_group(const Params& P) {
     bool fin = true;
 #pragma unroll
     for (int j = 0; j < D; ++j) fin = fin && (y0[j] == y0[j]) && (fabs(y0[j]) < __builtin_inf());
+    kp = 0;
     if (!inputs_valid<F>(P, i, s.in)) {
       finish(ST_BAD_INPUT);
       return;
     }
+    // Nodes at t0 take y0.
+    while (NODES && kp < P.K && node_time(P, kp, i) <= s.in.t0) {
+      put_node(kp, s.y);
+      ++kp;
+    }
+    if constexpr (NODES) t_next = kp < P.K ? node_time(P, kp, i) : __builtin_inf();
     if (!fin) {
       finish(ST_NONFINITE);
       return;
@@ -921,7 +978,22 @@ __device__ void solve_group(const Params& P) {
         if ((int64_t)s.nacc + s.nrej >= P.max_steps) {
           st = ST_MAX_STEPS;
         } else {
-          const Attempt a = group_attempt<TB, F>(P, cf, s, c);
+          const Attempt a = group_attempt<TB, F>(
+              P, cf, s, c, [&](double t_old, double hh, double y_old) {
+                if constexpr (!NODES) return;
+                while (t_next <= s.t) {
+                  const double tq = t_next;
+                  if (tq == s.t) {
+                    put_node(kp, s.y);
+                  } else if constexpr (DEFER) {
+                    put_node(kp, y_old, t_old, ((tq - t_old) / hh) * hh);
+                  } else {
+                    put_node(kp, group_dense<TB>(hh, (tq - t_old) / hh, s.y, s.k));
+                  }
+                  ++kp;
+                  t_next = kp < P.K ? node_time(P, kp, idx) : __builtin_inf();
+                }
+              });
           if constexpr (TAPE) {
             // every accepted step, the last one included
             if (a.accepted) {
@@ -1217,9 +1289,9 @@ __device__ __forceinline__ void forward_body(const Params& P, const SensParams& 
 template <class TB, class F, bool NODES, bool TAPE>
 __global__ void __launch_bounds__(256)
     __attribute__((amdgpu_waves_per_eu(FwdOccupancy<TB, F>::waves, 8))) solve_kernel(Params P) {
-  if constexpr (!NODES && F::D <= kGroup) {
+  if constexpr (F::D <= kGroup) {
     if ((int)blockIdx.x < P.wide_blocks) {  // uniform per workgroup
-      solve_group<TB, F, TAPE>(P);
+      solve_group<TB, F, NODES, TAPE>(P);
       return;
     }
   }

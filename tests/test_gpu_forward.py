@@ -206,6 +206,47 @@ def test_wide_groups_are_bitwise_identical(name, make, tab):
             np.testing.assert_array_equal(g[k], ref[k], err_msg=f"{k} wide={wide}")
 
 
+@pytest.mark.parametrize("tab", ["dopri5", "tsit5", "verner7"])
+@pytest.mark.parametrize("name,make", CASES, ids=[c[0] for c in CASES])
+def test_wide_groups_with_output_nodes(name, make, tab):
+    """Groups with output nodes: the outputs (dense values, exact hits, nodes
+    at t0 and t1, and for Verner 7 the deferred shortened steps), final
+    states and counts are bitwise those of one lane per trajectory, in both
+    output layouts."""
+    w = {**make(333), "tableau": tab}
+    for layout in ("dkn", "knd"):
+        ref = to_np(gpu_solve(w, api.Launch(out_layout=layout)))
+        assert np.all(ref["status"] == 0)
+        for wide in (37, 333):
+            g = to_np(gpu_solve(w, api.Launch(wide=wide, out_layout=layout)))
+            for k in ref:
+                np.testing.assert_array_equal(g[k], ref[k], err_msg=f"{k} wide={wide} {layout}")
+
+
+@pytest.mark.parametrize("tab", ["dopri5", "verner7"])
+def test_wide_group_outputs_of_stopped_and_invalid_trajectories(tab):
+    """Per-trajectory output times; a trajectory with a non-finite state, one
+    with an empty span and trajectories stopped by the step limit: the NaN
+    outputs past where each stopped, bitwise those of one lane each."""
+    n = 300
+    w = {**inputs.orbits_forward(n, seed=53), "tableau": tab}
+    tk = np.sort(np.random.default_rng(54).uniform(0.0, 50.0, (24, n)), axis=0)
+    tk[0, :] = 0.0                                   # a node at t0
+    y0 = w["y0"].copy()
+    y0[2, 5] = np.nan
+    t1 = np.full(n, float(np.max(w["t1"])))
+    t1[9] = float(np.min(w["t0"]))                   # empty span
+    w = {**w, "y0": y0, "t1": t1, "t_out": tk}
+    for L in (dict(), dict(max_steps=300)):
+        ref = to_np(gpu_solve(w, api.Launch(**L)))
+        g = to_np(gpu_solve(w, api.Launch(wide=n, **L)))
+        assert ref["status"][5] != 0
+        if L:
+            assert np.any(ref["status"] != 0) and np.any(np.isnan(ref["y_out"][:, -1, :]))
+        for k in ref:
+            np.testing.assert_array_equal(g[k], ref[k], err_msg=f"{k} {L}")
+
+
 def test_wide_groups_on_the_uneven_batch(orc):
     """Longest-first order with the 300 predicted-longest orbits of 20,000 on
     groups: bitwise equal to one lane each, and to the oracle on a sample."""
