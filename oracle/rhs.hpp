@@ -1,6 +1,9 @@
 // Oracle (test infrastructure only): right-hand sides f(t, y, theta),
 // templated on the scalar so the same text gives values (double) and, with
 // gso::Dual, the forward-mode products J_y S + df/dtheta of eq:sens.
+// Parity unpinned: the spin-orbit (beta) and spin-spin (sigma) terms of the
+// precession's radiation-reaction polynomial, which the paper does not
+// print; everything else here has a pin of its own.
 #pragma once
 #include <cmath>
 
@@ -89,7 +92,9 @@ void f_spinprec(double v, const T* y, const T* th, T* dy) {
   ds2[1] = Om2[2] * s2[0] - Om2[0] * s2[2];
   ds2[2] = Om2[0] * s2[1] - Om2[1] * s2[0];
   for (int i = 0; i < 3; ++i) dL[i] = -(v / eta) * (S1 * ds1[i] + S2 * ds2[i]);
-  // eq:prec-rr with the 2PN coefficients.
+  // eq:prec-rr with the 2PN coefficients.  beta and sigma have no pin of
+  // their own (parity unpinned): only the paper's printed attempt counts and
+  // angle errors, which depend on them weakly, check them.
   const double pi = 3.14159265358979323846;
   T beta = (chi1 * Ls1 * (T(113.0) * m1 * m1 + T(75.0) * eta) +
             chi2 * Ls2 * (T(113.0) * m2 * m2 + T(75.0) * eta)) / T(12.0);
