@@ -183,11 +183,10 @@ typedef struct gs_solve_args {
                             lane) in the same launch, for the long tail of
                             uneven ensembles; results are bit-identical to
                             one lane per trajectory.  0 = none.  Needs the
-                            queue schedule, and no tape or a store-mode
-                            tape (ckpt_every = 1), which the groups write
-                            record for record as one lane would (else
-                            GS_ERR_UNSUPPORTED); output nodes (K > 0) are
-                            written as one lane writes them.  The groups
+                            queue schedule (else GS_ERR_UNSUPPORTED); the
+                            tape (either mode) and output nodes are written
+                            record for record as one lane writes them.
+                            Explicit pairs only.  The groups
                             refill from their own queue; they and the single
                             lanes share the grid (the occupancy limit, or
                             `grid` when given), the single lanes keeping up

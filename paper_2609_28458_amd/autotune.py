@@ -26,8 +26,8 @@ CACHE = os.environ.get("GS_AUTOTUNE_CACHE",
 BLOCKS = (64, 128, 256)
 REFILLS = (1, 4, 8, 16, 64)
 # Trajectories at the head of the queue order run on 16-lane groups (wide):
-# tried on the best shapes when the call allows it (queue schedule, no tape
-# or a store-mode tape, at most 16 state components, an explicit pair).
+# tried on the best shapes when the call allows it (queue schedule, at most
+# 16 state components, an explicit pair).
 WIDES = (256, 512, 1024, 2048, 4096)
 CKPT = (1, 8, 32, 128)  # 1 = store mode: every accepted step on the tape
 
@@ -106,8 +106,7 @@ def tune_forward(prob: api.Problem, order=None, base: api.Launch | None = None,
                     sol.set_order(order)
                 scored.append((_time(lambda: sol.run()), shape))
     scored.sort(key=lambda x: x[0])
-    if (order is not None and base.ckpt_every in (0, 1) and prob.d <= 16
-            and prob.tableau != api.TABLEAU["rodas4"]):
+    if order is not None and prob.d <= 16 and prob.tableau != api.TABLEAU["rodas4"]:
         for _, shape0 in scored[:3]:
             for wide in WIDES:
                 if wide >= prob.n:
@@ -201,8 +200,8 @@ def tune_gradient(prob: api.Problem, make_cotangent, base: api.Launch | None = N
                   use_cache=True, order=None) -> api.Launch:
     """Fastest launch for forward-with-tape plus adjoint: the checkpoint
     interval k, and the launch shape of both passes (the base shape, two
-    waves per CU, one wave per SIMD; with a queue order and a store-mode
-    tape also the head of the order on 16-lane groups).  Run the adjoint
+    waves per CU, one wave per SIMD; with a queue order also the head of
+    the order on 16-lane groups in the forward).  Run the adjoint
     with the returned block and grid (``solve_vjp(..., block=, grid=)``).
 
     ``make_cotangent(sol)`` returns (ybar_final, ybar_out) for a solution.
@@ -228,8 +227,6 @@ def tune_gradient(prob: api.Problem, make_cotangent, base: api.Launch | None = N
     free = torch.cuda.mem_get_info(prob.y0.device)[0]
     for block, grid, wide in shapes:
         for k in CKPT:
-            if wide and k != 1:
-                continue  # groups write the store-mode tape only
             shape = {"block": block, "grid": grid, "wide": wide, "ckpt_every": k,
                      "ckpt_capacity": nmax // k + 2}
             L = api.Launch(**{**base.__dict__, **shape})

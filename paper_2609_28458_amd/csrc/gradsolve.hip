@@ -145,7 +145,7 @@ gs_status check_args(const gs_solve_args* a) {
   if (a->refill < 0 || a->refill > 64) return GS_ERR_INVALID;
   if (a->wide < 0) return GS_ERR_INVALID;
   if (a->out_layout != 0 && a->out_layout != 1) return GS_ERR_INVALID;
-  if (a->wide > 0 && (a->schedule != GS_SCHED_QUEUE || a->ckpt_every > 1))
+  if (a->wide > 0 && a->schedule != GS_SCHED_QUEUE)
     return GS_ERR_UNSUPPORTED;
   const gs_controller& c = a->ctrl;
   if (!(c.safety > 0.0) || !(c.alpha_min > 0.0) || !(c.alpha_max >= 1.0) ||

@@ -740,6 +740,7 @@ struct GroupTraj {
   double k[S];  // own component of each stage derivative
   double t, h, err_prev2;
   int32_t nacc, nrej, nanrun;
+  int32_t ck_left;  // accepted steps until the next checkpoint
 };
 
 // One attempt of a group: the single-lane attempt() component by component.
@@ -845,9 +846,11 @@ __device__ __forceinline__ double group_dense(double h, double sigma, double y_e
 // queue positions [0, n_wide) (the head of the order, longest first when
 // the caller sorts by predicted cost), one per 16-lane group, from their own
 // queue head (counters[3]).  Control mirrors the single-lane loop; every
-// ballot sits where all lanes of the wave execute it.  TAPE: a store-mode
-// tape (every accepted step), written as one lane writes it: lane c of the
-// group stores component c of each record, lane 0 its time and step.
+// ballot sits where all lanes of the wave execute it.  TAPE: the tape in
+// store mode (every accepted step) or checkpoint mode (every ckpt_every
+// accepted steps), written as one lane writes it: lane c of the group
+// stores component c of each record (and of k1 in a checkpoint), lane 0 its
+// time, step and controller memory.
 // NODES: output nodes, written as one lane writes them (lane c component c):
 // exact hits and dense values of pairs with a dense polynomial directly,
 // and for the other pairs the deferred shortened step's record (lane 0 its
@@ -888,6 +891,18 @@ __device__ void solve_group(const Params& P) {
     if (c == 0) {
       r[0] = s.t;
       r[1] = h_in;
+    }
+  };
+  auto put_checkpoint = [&](int cidx) {
+    double* r = P.tape + ((int64_t)ts * P.ckpt_cap + cidx) * ckpt_record_len<F>();
+    if (c == 0) {
+      r[0] = s.t;
+      r[1] = s.h;
+      r[2] = s.err_prev2;
+    }
+    if (c < D) {
+      r[3 + c] = s.y;
+      r[3 + D + c] = s.k[0];
     }
   };
   auto finish = [&](int32_t st) {
@@ -940,11 +955,14 @@ __device__ void solve_group(const Params& P) {
     F::f(s.t, y0, s.in.par, f0);
     s.k[0] = c < D ? pick<D>(f0, c) : 0.0;
     s.h = P.h0 > 0.0 ? dmin(P.h0, s.in.t1 - s.in.t0) : initial_step<TB, F>(s.in, y0, f0);
+    s.ck_left = P.ckpt_every;
     if constexpr (TAPE) {
       if (P.ckpt_cap <= 0)
         overflow = true;
-      else
+      else if (P.store)
         put_record(0, 0.0);
+      else
+        put_checkpoint(0);
     }
   };
 
@@ -994,11 +1012,22 @@ __device__ void solve_group(const Params& P) {
                   t_next = kp < P.K ? node_time(P, kp, idx) : __builtin_inf();
                 }
               });
-          if constexpr (TAPE) {
+          if constexpr (!TAPE) {
+          } else if (P.store) {
             // every accepted step, the last one included
             if (a.accepted) {
               if (s.nacc < P.ckpt_cap)
                 put_record(s.nacc, a.h_used);
+              else
+                overflow = true;
+            }
+          } else if (!a.finished) {
+            s.ck_left -= a.accepted ? 1 : 0;
+            if (s.ck_left == 0) {
+              s.ck_left = P.ckpt_every;
+              const int cidx = s.nacc / P.ckpt_every;
+              if (cidx < P.ckpt_cap)
+                put_checkpoint(cidx);
               else
                 overflow = true;
             }

@@ -132,12 +132,14 @@ def test_status_strings():
     assert api.gs_version() == "0.2.0"
 
 
-def test_wide_needs_queue_schedule_without_checkpoint_tape():
-    # groups of lanes take the queue schedule, no tape or a store-mode tape
-    for kw in (dict(wide=8, schedule=1), dict(wide=8, ckpt_every=4, ckpt_capacity=10)):
-        assert api.lib().gs_solve(C.byref(_args(**kw))) == 2
-    # output nodes pass the host checks (the call then fails only for want of a GPU)
-    assert api.lib().gs_solve(C.byref(_args(wide=8, K=3, t_out=0x1000, y_out=0x1000))) != 2
+def test_wide_needs_the_queue_schedule():
+    # groups of lanes take the queue schedule
+    assert api.lib().gs_solve(C.byref(_args(wide=8, schedule=1))) == 2
+    # output nodes and both tape modes pass the host checks (the call then fails
+    # only for want of a GPU)
+    for kw in (dict(wide=8, K=3, t_out=0x1000, y_out=0x1000),
+               dict(wide=8, ckpt_every=4, ckpt_capacity=10)):
+        assert api.lib().gs_solve(C.byref(_args(**kw))) != 2
 
 
 def test_sens_argument_checks():

@@ -293,6 +293,49 @@ def test_output_layout_knd(tab):
                 np.testing.assert_array_equal(b[k], a[k], err_msg=k)
 
 
+@pytest.mark.parametrize("tab", ["dopri5", "verner7"])
+def test_wide_groups_write_the_checkpoint_tape(tab):
+    """Groups with a checkpoint-mode tape (every 5 accepted steps, PI control
+    so that the controller memory is on it too): the tape bytes and results
+    of one lane per trajectory, the adjoint's replay lands on every next
+    checkpoint, and the gradients are the same; with a tape too short, the
+    same overflow status."""
+    n = 2000
+    w = inputs.orbits_uneven(n=n, seed=55)
+    w = {**w, "t1": np.minimum(w["t1"], 40.0), "tableau": tab}
+    order = np.argsort(-inputs.predicted_cost(w), kind="stable")
+    p = api.make_problem(w["rhs"], tab, w["y0"], w["theta"], w["t0"], w["t1"], w["rtol"],
+                         w["atol"])
+    ctl = dict(beta1=0.7 / 5, beta2=0.4 / 5) if tab == "dopri5" else {}
+    nmax = int(api.solve(p, api.Launch(**ctl)).n_accepted.max())
+    for cap in (nmax // 5 + 2, 5):
+        sols = []
+        for wide in (0, 400):
+            s = api.Solution(p, api.Launch(block=128, ckpt_every=5, ckpt_capacity=cap, wide=wide,
+                                           **ctl))
+            s.set_order(order)
+            s.workspace.zero_()
+            s.run()
+            sols.append(s)
+        torch.cuda.synchronize()
+        a, b = sols
+        for k in ("y_final", "n_accepted", "n_rejected", "status"):
+            assert torch.equal(getattr(a, k), getattr(b, k)), k
+        tape_bytes = n * cap * (3 + 2 * 6) * 8
+        assert torch.equal(a.workspace[256:256 + tape_bytes], b.workspace[256:256 + tape_bytes])
+        if cap == 5:
+            assert bool((a.status == 4).any())
+            continue
+        assert bool((a.status == 0).all())
+        yb = torch.ones((1, 6, n), dtype=torch.float64, device="cuda")
+        ga = api.solve_vjp(a, ybar_final=yb)
+        gb = api.solve_vjp(b, ybar_final=yb)
+        torch.cuda.synchronize()
+        assert a.replay_mismatches() == 0 and b.replay_mismatches() == 0
+        for x, y in zip(ga, gb):
+            assert torch.equal(x, y)
+
+
 def test_wide_groups_write_the_store_tape():
     """Groups with a store-mode tape: the tape bytes, results and statuses of
     one lane per trajectory, and the same adjoint gradients from it; with a
