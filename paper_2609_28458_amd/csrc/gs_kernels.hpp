@@ -1376,6 +1376,14 @@ __host__ __device__ constexpr bool stage_feeds_step(int j) {
     if (TB::A(i, j) != 0.0) return true;
   return false;
 }
+// The first stage of the reverse sweep that adds to stage l's cotangent (the
+// last feeding stage i > l with a_il != 0), or -1 if none does.
+template <class TB>
+__host__ __device__ constexpr int first_touch(int l) {
+  for (int i = TB::S - 1; i > l; --i)
+    if (stage_feeds_step<TB>(i) && TB::A(i, l) != 0.0) return i;
+  return -1;
+}
 
 // Reverse of one explicit RK step of length h from (t, y) (the transpose of
 // eq:stage-sens with h fixed).  lam[r] enters as the cotangent of y+ and
@@ -1449,6 +1457,56 @@ __device__ __forceinline__ void reverse_step(const Inputs<F>& in, double t, doub
   }
 #pragma unroll
   for (int r = 0; r < R; ++r) {
+    if constexpr (!NODES) {
+      // No output seeds: stage j's cotangent (h b_j lam plus what later
+      // stages add) is formed when it is first added to, so that only the
+      // accumulators of stages still ahead in the sweep are live (seven of
+      // ten for Verner 7 instead of all).  Same operations in the same order
+      // as the form below.
+      double kb[S][D];
+      double yb[D];
+#pragma unroll
+      for (int c = 0; c < D; ++c) yb[c] = lam[r][c];
+      rfor<S>([&](auto J) {
+        constexpr int j = decltype(J)::value;
+        if constexpr (stage_feeds_step<TB>(j)) {
+          double Yj[D], ybj[D], kbj[D];
+          if constexpr (j == 0) {
+#pragma unroll
+            for (int c = 0; c < D; ++c) Yj[c] = y[c];
+          } else {
+#pragma unroll
+            for (int c = 0; c < D; ++c) Yj[c] = Ys(j, c);
+          }
+#pragma unroll
+          for (int c = 0; c < D; ++c) {
+            if constexpr (first_touch<TB>(j) >= 0)
+              kbj[c] = kb[j][c];
+            else
+              kbj[c] = (h * TB::B(j)) * lam[r][c];
+          }
+          F::vjp(t + TB::C(j) * h, Yj, in.th, in.par, kbj, ybj, thb[r]);
+#pragma unroll
+          for (int c = 0; c < D; ++c) yb[c] += ybj[c];
+          sfor<j>([&](auto L) {
+            constexpr int l = decltype(L)::value;
+            constexpr double a = TB::A(j, l);
+            if constexpr (a != 0.0) {
+#pragma unroll
+              for (int c = 0; c < D; ++c) {
+                if constexpr (first_touch<TB>(l) == j)
+                  kb[l][c] = fma(h * a, ybj[c], (h * TB::B(l)) * lam[r][c]);
+                else
+                  kb[l][c] = fma(h * a, ybj[c], kb[l][c]);
+              }
+            }
+          });
+        }
+      });
+#pragma unroll
+      for (int c = 0; c < D; ++c) lam[r][c] = yb[c];
+      continue;
+    }
     double kb[S][D];
     double yb[D];
     sfor<S>([&](auto J) {
