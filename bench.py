@@ -781,7 +781,10 @@ def stiff_bench(torch, api, inputs, autotune):
         prob = mk(api, w)
         feats = stiff_features(torch, w, prob)
         _, cost = wall_ms(lambda: autotune.pilot_cost(prob, feats), torch)
-        sol = api.Solution(prob, api.Launch())
+        tmp = api.Solution(prob, api.Launch())
+        order = tmp.queue_order(cost).clone()
+        del tmp
+        sol = api.Solution(prob, autotune.tune_forward(prob, order=order, use_cache=False))
         ms = timed(lambda: (sol.queue_order(cost), sol.run()), 3, 1, torch)
         attempts = int((sol.n_accepted.to(torch.int64) + sol.n_rejected).sum())
         tf = fpa * attempts / (ms * 1e-3) / 1e12

@@ -245,9 +245,11 @@ void gs_default_args(gs_solve_args* args);
  * of the workspace) and, with a tape, the adjoint's per-lane buffers for
  * min(n rounded up to 256, 131072) lanes: the running cotangents (d + p
  * doubles) and, in checkpoint mode, the replay scratch (ckpt_every steps of
- * 2 + d doubles); for GS_VERNER7 with K > 0 also (2 + d) K n doubles for
- * the outputs' shortened steps (start time, length and start state of each),
- * which gs_solve evaluates after the solve kernel (one thread per output).
+ * 2 + d doubles); for an explicit pair with K > 0 also (2 + d) K n doubles
+ * for the outputs inside steps (start time, length and start state of the
+ * step that passes each), which gs_solve evaluates after the solve kernel
+ * (one thread per output: the dense polynomial of the step taken again, or
+ * Verner 7's shortened step).
  * Returns 0 for an invalid `args`. */
 size_t gs_workspace_bytes(const gs_solve_args* args);
 
@@ -276,9 +278,10 @@ gs_status gs_solve(const gs_solve_args* args);
  * (4 KiB per GPU, held until the process ends) instead of `workspace`, which
  * is ignored.  Forward solves only: ckpt_every must be 0 (a tape would have
  * to outlive the call for gs_solve_vjp, which reads the caller's workspace),
- * else GS_ERR_UNSUPPORTED; a request needing more than the static buffer
- * (gs_workspace_bytes above 4 KiB: GS_VERNER7 with (2 + d) K n > 480, whose
- * outputs' shortened steps keep (2 + d) K n doubles) is GS_ERR_TOO_LARGE, returned
+ * else GS_ERR_UNSUPPORTED.  The deferred output records (2 + d) K n doubles
+ * are kept in the buffer when they fit ((2 + d) K n <= 480); otherwise
+ * GS_DOPRI5 and GS_TSIT5 evaluate their outputs inside the solve kernel (the
+ * same values, bit for bit) and GS_VERNER7 is GS_ERR_TOO_LARGE, returned
  * before anything is launched.  Allocates nothing.  Every call on one GPU shares that
  * buffer (the counters are reset by a kernel at the start of each call), so
  * calls that overlap on one GPU -- on different streams, or from different

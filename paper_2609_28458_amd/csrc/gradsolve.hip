@@ -83,13 +83,16 @@ struct Layout {
   int64_t adj_lanes;
 };
 
-// Outputs of the plain solve that are deferred shortened steps (explicit
-// pairs without a dense polynomial, K > 0): pending [K][n][2 + d] doubles.
-bool defers_outputs(const gs_solve_args* a) {
-  return a->tableau == GS_VERNER7 && a->K > 0 && a->rhs >= 0 && a->rhs < kNumExplicitRhs;
+// Outputs of the plain solve of an explicit pair (K > 0) are deferred to the
+// output kernel: pending [K][n][2 + d] doubles.  `defer` false (the
+// no-allocation entry point, when they do not fit) keeps a polynomial pair's
+// outputs in the solve kernel; a pair without a polynomial always defers.
+bool defers_outputs(const gs_solve_args* a, bool defer) {
+  return a->K > 0 && a->rhs >= 0 && a->rhs < kNumExplicitRhs &&
+         (defer || a->tableau == GS_VERNER7);
 }
 
-Layout layout_of(const gs_solve_args* a) {
+Layout layout_of(const gs_solve_args* a, bool defer = true) {
   Layout L;
   const int d = rhs_dim(a->rhs);
   L.tape_off = kCounterBytes;
@@ -111,7 +114,8 @@ Layout layout_of(const gs_solve_args* a) {
   L.scratch_off = align256(L.tape_off + L.tape_bytes);
   L.adj_off = align256(L.scratch_off + L.scratch_bytes);
   L.pending_off = align256(L.adj_off + L.adj_bytes);
-  L.pending_bytes = defers_outputs(a) ? (size_t)(2 + d) * (size_t)a->K * (size_t)a->n * 8 : 0;
+  L.pending_bytes =
+      defers_outputs(a, defer) ? (size_t)(2 + d) * (size_t)a->K * (size_t)a->n * 8 : 0;
   // With a tape, each trajectory's tape slot (the queue position the
   // forward took it from), read by the adjoint and dense queries.
   L.slot_off = align256(L.pending_off + L.pending_bytes);
@@ -121,7 +125,7 @@ Layout layout_of(const gs_solve_args* a) {
 }
 
 // Host-side argument checks (everything that needs no device memory).
-gs_status check_args(const gs_solve_args* a) {
+gs_status check_args(const gs_solve_args* a, bool defer = true) {
   if (!a) return GS_ERR_INVALID;
   if (a->rhs < 0 || a->rhs >= kNumRhs || a->tableau < 0 || a->tableau >= kNumTab)
     return GS_ERR_INVALID;
@@ -156,7 +160,7 @@ gs_status check_args(const gs_solve_args* a) {
                       c.beta2 != 0.0))
     return GS_ERR_UNSUPPORTED;
   if (!a->workspace) return GS_ERR_WORKSPACE;
-  if (a->workspace_bytes < layout_of(a).total) return GS_ERR_WORKSPACE;
+  if (a->workspace_bytes < layout_of(a, defer).total) return GS_ERR_WORKSPACE;
   if (((uintptr_t)a->workspace & 255) != 0) return GS_ERR_WORKSPACE;
   return GS_OK;
 }
@@ -180,7 +184,7 @@ bool fast_controller_exact(const gs_solve_args* a) {
   return c.safety * g >= c.alpha_max && c.safety / g <= c.alpha_min;
 }
 
-Params make_params(const gs_solve_args* a) {
+Params make_params(const gs_solve_args* a, bool defer = true) {
   Params P;
   std::memset(&P, 0, sizeof P);
   P.n = a->n;
@@ -212,7 +216,7 @@ Params make_params(const gs_solve_args* a) {
   P.ckpt_every = a->ckpt_every;
   P.ckpt_cap = a->ckpt_capacity;
   P.store = a->ckpt_every == 1 ? 1 : 0;
-  const Layout L = layout_of(a);
+  const Layout L = layout_of(a, defer);
   char* ws = static_cast<char*>(a->workspace);
   P.counters = reinterpret_cast<unsigned long long*>(ws);
   P.tape = a->ckpt_every > 0 ? reinterpret_cast<double*>(ws + L.tape_off) : nullptr;
@@ -270,7 +274,8 @@ const Ops& ops(int rhs, int tab) {
 // queue mode fills every CU to its occupancy limit (or takes the caller's
 // grid) but never launches more lanes than trajectories.  `limit` is the
 // grid before that last clip: the most workgroups the launch may hold.
-void solve_shape(const gs_solve_args* a, int* grid, int* block, int64_t* limit = nullptr) {
+void solve_shape(const gs_solve_args* a, int* grid, int* block, int64_t* limit = nullptr,
+                 bool defer = true) {
   const int b = a->block > 0 ? a->block : 256;
   const int64_t need = (a->n + b - 1) / b;
   int64_t lim = need;
@@ -281,9 +286,10 @@ void solve_shape(const gs_solve_args* a, int* grid, int* block, int64_t* limit =
     *grid = (int)std::min<int64_t>(a->grid, need);
   } else {
     int per_cu = 0;
-    const void* fn =
-        is_stiff(a) ? gs_host::stiff_solve_fn(a->rhs)
-                    : ops(a->rhs, a->tableau).solve_fn[a->K > 0][a->ckpt_every > 0];
+    const gs_host::Ops& o = ops(a->rhs, a->tableau);
+    const void* fn = is_stiff(a) ? gs_host::stiff_solve_fn(a->rhs)
+                     : (a->K > 0 && !defers_outputs(a, defer)) ? o.solve_fn_inloop
+                                                                : o.solve_fn[a->K > 0][a->ckpt_every > 0];
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, b, 0) != hipSuccess ||
         per_cu < 1)
       per_cu = 1;
@@ -314,9 +320,9 @@ void wide_split(int64_t n, int64_t n_wide, int block, int64_t limit, int* wide_b
   *grid = (int)(w + single);
 }
 
-gs_status launch_solve_all(const gs_solve_args* a) {
+gs_status launch_solve_all(const gs_solve_args* a, bool defer = true) {
   hipStream_t s = static_cast<hipStream_t>(a->stream);
-  const Params P = make_params(a);
+  const Params P = make_params(a, defer);
   Params P2 = P;
   hipLaunchKernelGGL(reset_queues_kernel, dim3(1), dim3(64), 0, s, P.counters, (long long)P.n_wide);
   if (a->order)
@@ -324,7 +330,7 @@ gs_status launch_solve_all(const gs_solve_args* a) {
                        (int32_t)GS_TRAJ_NOT_RUN);
   int grid = 0, block = 0;
   int64_t limit = 0;
-  solve_shape(a, &grid, &block, &limit);
+  solve_shape(a, &grid, &block, &limit, defer);
   if (is_stiff(a)) {
     gs_host::launch_stiff(a->rhs, P, grid, block, s);
     return hipGetLastError() == hipSuccess ? GS_OK : GS_ERR_HIP;
@@ -423,15 +429,20 @@ gs_status gs_solve_noalloc(const gs_solve_args* a) {
   gs_solve_args c = *a;
   c.workspace = nullptr;
   c.workspace_bytes = kStaticScratchBytes;
-  if (c.rhs >= 0 && c.rhs < kNumRhs && c.n >= 0 && layout_of(&c).total > kStaticScratchBytes)
-    return GS_ERR_TOO_LARGE;
+  // Deferred outputs only where their records fit; a pair with a dense
+  // polynomial then evaluates its outputs in the solve kernel instead.
+  bool defer = true;
+  if (c.rhs >= 0 && c.rhs < kNumRhs && c.n >= 0 && layout_of(&c).total > kStaticScratchBytes) {
+    defer = false;
+    if (layout_of(&c, false).total > kStaticScratchBytes) return GS_ERR_TOO_LARGE;
+  }
   void* p = nullptr;
   const gs_status sp = static_scratch(&p);
   if (sp != GS_OK) return sp;
   c.workspace = p;
-  const gs_status st = check_args(&c);
+  const gs_status st = check_args(&c, defer);
   if (st != GS_OK || c.n == 0) return st;
-  return launch_solve_all(&c);
+  return launch_solve_all(&c, defer);
 }
 
 size_t gs_queue_order_workspace_bytes(int64_t n) {

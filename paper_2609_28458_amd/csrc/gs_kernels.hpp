@@ -451,21 +451,25 @@ __device__ __forceinline__ Attempt attempt(const Params& P, Traj<TB, F, T>& s,
   a.accepted = acc;
   const double t_new = last ? s.in.t1 : s.t + hh;
   a.t_new = t_new;
+  // The step's start state goes to on_accept where an output may need it:
+  // a shortened step, or a deferred output (plain solves).  A dual-number
+  // solve of a polynomial pair needs only the end state.
+  constexpr bool KEEP_START = !TB::POLY_DENSE || std::is_same<T, double>::value;
   T ystart[D];
   double probe = 0.0;  // becomes NaN if any component of y+ is not finite
 #pragma unroll
   for (int c = 0; c < D; ++c) {
-    if constexpr (!TB::POLY_DENSE) ystart[c] = s.y[c];
+    if constexpr (KEEP_START) ystart[c] = s.y[c];
     probe = fma(ad::val(yn[c]), 0.0, probe);
     s.y[c] = ad::select(acc, yn[c], s.y[c]);
   }
   const bool fin = probe == 0.0;
   s.t = acc ? t_new : s.t;
   if (acc) {
-    if constexpr (TB::POLY_DENSE) {
-      on_accept(s, a.t_start, hh, s.y);
-    } else {
+    if constexpr (KEEP_START) {
       on_accept(s, a.t_start, hh, ystart);
+    } else {
+      on_accept(s, a.t_start, hh, s.y);
     }
   }
   if constexpr (TB::FSAL && !std::is_same<T, double>::value) {
@@ -852,13 +856,13 @@ __device__ __forceinline__ double group_dense(double h, double sigma, double y_e
 // stores component c of each record (and of k1 in a checkpoint), lane 0 its
 // time, step and controller memory.
 // NODES: output nodes, written as one lane writes them (lane c component c):
-// exact hits and dense values of pairs with a dense polynomial directly,
-// and for the other pairs the deferred shortened step's record (lane 0 its
-// start time and length, lane c component c of its start state).
-template <class TB, class F, bool NODES, bool TAPE>
+// exact hits directly, the others as deferred records (lane 0 the step's
+// start time and length, lane c component c of its start state), or with
+// INLOOP (a pair with a dense polynomial, no pending array) the dense value.
+template <class TB, class F, bool NODES, bool TAPE, bool INLOOP>
 __device__ void solve_group(const Params& P) {
   constexpr int D = F::D;
-  constexpr bool DEFER = NODES && !TB::POLY_DENSE;
+  constexpr bool DEFER = NODES && !INLOOP;
   const int lane = threadIdx.x & 63;
   const int c = lane & (kGroup - 1);
   const int first = lane & ~(kGroup - 1);  // the group's lane 0
@@ -1004,8 +1008,9 @@ __device__ void solve_group(const Params& P) {
                   if (tq == s.t) {
                     put_node(kp, s.y);
                   } else if constexpr (DEFER) {
-                    put_node(kp, y_old, t_old, ((tq - t_old) / hh) * hh);
-                  } else {
+                    put_node(kp, y_old, t_old,
+                             TB::POLY_DENSE ? hh : ((tq - t_old) / hh) * hh);
+                  } else if constexpr (TB::POLY_DENSE) {
                     put_node(kp, group_dense<TB>(hh, (tq - t_old) / hh, s.y, s.k));
                   }
                   ++kp;
@@ -1090,17 +1095,24 @@ __device__ __forceinline__ void seed_inputs(const SensParams& SP, const Inputs<F
 // that many queue positions and the idle lanes take them (ballot + prefix
 // count).  In static mode lane g integrates trajectory g and is never
 // refilled.
-template <class TB, class F, class T, bool NODES, bool TAPE>
+template <class TB, class F, class T, bool NODES, bool TAPE, bool INLOOP = false>
 __device__ __forceinline__ void forward_body(const Params& P, const SensParams& SP) {
   constexpr int D = F::D;
   constexpr bool SENS = !std::is_same<T, double>::value;
   constexpr int M = ad::width<T>::value;
   static_assert(!(SENS && TAPE), "sensitivity solves keep no tape");
-  // Outputs of a pair without a dense polynomial are shortened steps; the
-  // plain solve defers them to short_step_kernel (one thread per output,
-  // after the solve), so that their stages never widen the attempt loop's
-  // register allocation.  The host then supplies the pending array.
-  constexpr bool DEFER = NODES && !SENS && !TB::POLY_DENSE;
+  // The plain solve defers outputs inside a step to short_step_kernel (one
+  // thread per output, after the solve): it records the step's start time,
+  // length and start state, and the later kernel takes the step again (a
+  // pair with a dense polynomial) or the shortened step (a pair without).
+  // In the attempt loop an output then costs a few stores instead of the
+  // dense evaluation, which a wavefront otherwise runs with most lanes idle
+  // on nearly every attempt once outputs are dense.  The host supplies the
+  // pending array; where it has no room for it (INLOOP, a pair with a dense
+  // polynomial only) the outputs are evaluated in the loop, as they are for
+  // sensitivity solves.
+  static_assert(!INLOOP || TB::POLY_DENSE, "in-loop outputs need a dense polynomial");
+  constexpr bool DEFER = NODES && !SENS && !INLOOP;
   Traj<TB, F, T> s;
   int64_t idx = -1, ts = 0;  // trajectory and its tape slot
   int32_t kp = 0;
@@ -1270,9 +1282,10 @@ __device__ __forceinline__ void forward_body(const Params& P, const SensParams& 
                   if (tq == sa.t) {
                     put_node(kp, sa.y);
                   } else if constexpr (DEFER) {
-                    // the shortened step from (t_old, ys) runs later, in
-                    // short_step_kernel; here its start and length
-                    put_node(kp, ys, t_old, ((tq - t_old) / hh) * hh);
+                    // the step from (t_old, ys) is taken again later, in
+                    // short_step_kernel; here its start and length (the
+                    // shortened length for a pair without a polynomial)
+                    put_node(kp, ys, t_old, TB::POLY_DENSE ? hh : ((tq - t_old) / hh) * hh);
                   } else {
                     T out[D];
                     dense_value<TB, F>(sa.in.par, t_old, hh, (tq - t_old) / hh, sa.y, ys, sa.k,
@@ -1315,25 +1328,30 @@ __device__ __forceinline__ void forward_body(const Params& P, const SensParams& 
 
 // Plain forward solve (and, with wide > 0, the head of the queue on 16-lane
 // groups).
-template <class TB, class F, bool NODES, bool TAPE>
+// INLOOP: outputs of a pair with a dense polynomial evaluated in the loop
+// (no pending array).
+template <class TB, class F, bool NODES, bool TAPE, bool INLOOP = false>
 __global__ void __launch_bounds__(256)
     __attribute__((amdgpu_waves_per_eu(FwdOccupancy<TB, F>::waves, 8))) solve_kernel(Params P) {
   if constexpr (F::D <= kGroup) {
     if ((int)blockIdx.x < P.wide_blocks) {  // uniform per workgroup
-      solve_group<TB, F, NODES, TAPE>(P);
+      solve_group<TB, F, NODES, TAPE, INLOOP>(P);
       return;
     }
   }
-  forward_body<TB, F, double, NODES, TAPE>(P, SensParams{});
+  forward_body<TB, F, double, NODES, TAPE, INLOOP>(P, SensParams{});
 }
 
-// The deferred outputs of a pair without a dense polynomial: output kk of
-// trajectory i is one step of the pair of length hs from the step start
-// (t_start, y_start) that the solve recorded in pending, with k[0] =
-// f(t_start, y_start) evaluated afresh (the value the solve's own step
-// started from, so the result is the shortened step of eq:dense bit for
-// bit).  One thread per output, over [K][n] (consecutive threads write
-// consecutive trajectories of y_out); hs = 0 marks an output the solve
+// The deferred outputs of a plain solve: for output kk of trajectory i the
+// solve recorded in pending the start (t_start, y_start) and a length hs.
+// A pair with a dense polynomial takes the step of length hs again and
+// evaluates the polynomial of eq:dense at the output's sigma; a pair without
+// one takes the shortened step of length hs.  k[0] = f(t_start, y_start) is
+// evaluated afresh: for a first-same-as-last pair it is the value the solve
+// carried over from the previous step (the same function at the same time
+// and state), so every output equals the one the solve would have written,
+// bit for bit.  One thread per output, over [K][n] (consecutive threads
+// write consecutive trajectories of y_out); hs = 0 marks an output the solve
 // already wrote.
 template <class TB, class F>
 __global__ void __launch_bounds__(256) short_step_kernel(Params P) {
@@ -1353,7 +1371,14 @@ __global__ void __launch_bounds__(256) short_step_kernel(Params P) {
 #pragma unroll
   for (int c = 0; c < D; ++c) y[c] = rec[2 + c];
   F::f(t_start, y, in.par, k[0]);
-  rk_stages<TB, F>(in.par, t_start, hs, y, k, out);
+  if constexpr (TB::POLY_DENSE) {
+    double yend[D];
+    rk_stages<TB, F>(in.par, t_start, hs, y, k, yend);
+    const double tq = node_time(P, (int)kk, i);
+    dense_value<TB, F>(in.par, t_start, hs, (tq - t_start) / hs, yend, y, k, out);
+  } else {
+    rk_stages<TB, F>(in.par, t_start, hs, y, k, out);
+  }
 #pragma unroll
   for (int c = 0; c < D; ++c)
     P.y_out[P.out_layout ? (kk * P.n + i) * D + c : ((int64_t)c * P.K + kk) * P.n + i] = out[c];

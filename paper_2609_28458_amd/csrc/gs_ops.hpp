@@ -14,6 +14,9 @@ struct Ops {
   // The forward kernel variants, [output nodes][tape], for the occupancy
   // query of the one that runs.
   const void* solve_fn[2][2];
+  // The variant with outputs evaluated in the loop (pairs with a dense
+  // polynomial, no pending array), or null.
+  const void* solve_fn_inloop;
   void (*solve)(const gs::Params&, int grid, int block, hipStream_t);
   // grid <= 0: no launch; writes the blocks per CU of the variant that
   // would run to *V.occupancy_out.
