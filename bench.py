@@ -477,14 +477,14 @@ def c1_forward(torch, api, inputs, autotune):
     ms_c = timed(lambda: csol.run(), 3, 1, torch)
     fl_c = (att_c * FLOPS_PER_ATTEMPT[("dopri5", "loghalo")]
             + nc * cprob.K * FLOPS_PER_NODE[("dopri5", "loghalo")])
-    ach_c = fl_c / (ms_c * 1e-3) / 1e12
+    ach_c = fl_c / (min(ms_c, ms_dkn) * 1e-3) / 1e12
     res["at_1m"] = {"workload": "the same recipe at 1,000,000 orbits, longest first",
                     "ms_out_layout_knd": round(ms_c, 3), "ms_out_layout_dkn": round(ms_dkn, 3),
                     "attempts": att_c, "achieved": round(ach_c, 3), "unit": "TFLOP/s",
                     "frac": round(ach_c / PEAK_FP64_VECTOR_TFLOPS, 4),
                     "all_ok": bool((csol.status == 0).all())}
-    log(f"[bench] c1 at 10^6: {ms_c:.3f} ms ({ach_c / PEAK_FP64_VECTOR_TFLOPS:.1%}), "
-        f"[d][K][n] {ms_dkn:.3f} ms")
+    log(f"[bench] c1 at 10^6: [K][n][d] {ms_c:.3f} ms, [d][K][n] {ms_dkn:.3f} ms "
+        f"({ach_c / PEAK_FP64_VECTOR_TFLOPS:.1%} at the faster)")
     del csol
     return res
 
