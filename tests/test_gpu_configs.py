@@ -149,8 +149,8 @@ def test_spin_precession_full_size(orc):
     bar = np.maximum(1e-9, 5.0 * self_d)
     e = np.maximum(rel_err(g["y_final"][:, idx], o["y_final"]).max(axis=0),
                    rel_err(g["y_out"][:, :, idx], o["y_out"]).max(axis=(0, 1)))
-    record("precession 10^6 at 3.16e-9, 1,050 sampled incl. the 50 longest: max error",
-           e.max(), 1e-9)
+    record("precession 10^6 at 3.16e-9, 1,050 sampled incl. the 50 longest: max error "
+           "(bar: that binary's own)", e.max(), bar[np.argmax(e)])
     record("  same, error over the binary's own bar (<= 1)", (e / bar).max(), 1.0)
     record("  same, binaries whose own rounding response exceeds 2e-10", (self_d > 2e-10).sum(),
            len(idx))
@@ -163,6 +163,52 @@ def test_spin_precession_full_size(orc):
     print(f"precession from r=1000 at 3.16e-9: P99 angle error {_p99(eps):.3e} rad on 100 "
           f"binaries; mean attempts {np.mean(g['n_accepted'] + g['n_rejected']):.0f}")
     assert np.all(np.isfinite(eps))
+
+
+def test_spin_precession_headline_configuration(orc):
+    """The benchmark's headline as it is timed: 10^6 binaries from r = 1000
+    at 1e-11 with 32 outputs, longest first by the device order of a
+    pilot-fitted cost, refill at one idle lane.  Parity on 400 sampled
+    binaries plus the 20 that took the most attempts, each within 1e-9 or
+    five times the oracle's own response to rounding-level parameter
+    changes (the largest of three), with identical step counts."""
+    from paper_2609_28458_amd import autotune
+
+    w = inputs.spin_precession()
+    w.update(rtol=1e-11, atol=1e-11)
+    n = w["y0"].shape[1]
+    prob = _prob(w)
+    pilot = _prob({**w, "t0": 100.0 ** -0.5, "t_out": None})
+    y, th = pilot.y0, pilot.theta
+    feats = torch.stack([torch.log(th[0]), th[1], th[2], (y[0:3] * y[3:6]).sum(0),
+                         (y[0:3] * y[6:9]).sum(0), (y[3:6] * y[6:9]).sum(0)])
+    cost = autotune.pilot_cost(pilot, feats).contiguous()
+    sol = api.Solution(prob, api.Launch(refill=1))
+    sol.queue_order(cost)
+    sol.run()
+    torch.cuda.synchronize()
+    g = to_np(sol)
+    assert np.all(g["status"] == 0)
+    longest = np.argsort(-(g["n_accepted"] + g["n_rejected"]))[:20]
+    idx = np.unique(np.concatenate([np.random.default_rng(14).choice(n, 400, replace=False),
+                                    longest]))
+    o = oracle_solve(orc, w, idx)
+    np.testing.assert_array_equal(g["n_accepted"][idx], o["n_accepted"])
+    np.testing.assert_array_equal(g["n_rejected"][idx], o["n_rejected"])
+    self_d = np.zeros(len(idx))
+    for rel in (-1e-15, 1e-15, 4e-16):
+        o2 = orc.solve(w["rhs"], w["tableau"], w["y0"][:, idx], w["theta"][:, idx] * (1.0 + rel),
+                       w["t0"], w["t1"], w["rtol"], w["atol"], w["t_out"])
+        self_d = np.maximum(self_d, np.maximum(
+            np.abs(o2["y_final"] - o["y_final"]).max(axis=0),
+            np.abs(o2["y_out"] - o["y_out"]).max(axis=(0, 1))))
+    bar = np.maximum(1e-9, 5.0 * self_d)
+    e = np.maximum(rel_err(g["y_final"][:, idx], o["y_final"]).max(axis=0),
+                   rel_err(g["y_out"][:, :, idx], o["y_out"]).max(axis=(0, 1)))
+    record("precession headline (10^6 at 1e-11, device order, refill 1), 420 sampled incl. "
+           "the 20 longest: max error (bar: that binary's own)", e.max(), bar[np.argmax(e)])
+    record("  same, error over the binary's own bar (<= 1)", (e / bar).max(), 1.0)
+    assert np.all(e <= bar), (e.max(), (e / bar).max())
 
 
 def test_spin_precession_paper_setting(orc):
