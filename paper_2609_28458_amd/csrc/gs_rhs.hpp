@@ -176,6 +176,9 @@ struct SpinPrec {
   template <class T>
   struct ParT {
     T q, iq, eta, ieta, S1, S2, cq1, cq2, c1, c2, sig, b2, b4c;
+    // Products of the above that f folds into its coefficients:
+    // -3 q S1, -3 S2, -3 S1, -3 S2 / q, 721 sig, -247 sig, (32/5) eta.
+    T m3qS1, m3S2, m3S1, m3iqS2, sig721, sig247, k64e;
   };
   using Par = ParT<double>;
   template <class T>
@@ -197,6 +200,13 @@ struct SpinPrec {
     p.sig = p.eta * chi1 * chi2 * (1.0 / 48.0);
     p.b2 = -(743.0 / 336.0 + 2.75 * p.eta);
     p.b4c = 34103.0 / 18144.0 + (13661.0 / 2016.0) * p.eta + (59.0 / 18.0) * p.eta * p.eta;
+    p.m3qS1 = -3.0 * (q * p.S1);
+    p.m3S2 = -3.0 * p.S2;
+    p.m3S1 = -3.0 * p.S1;
+    p.m3iqS2 = -3.0 * (p.S2 * p.iq);
+    p.sig721 = 721.0 * p.sig;
+    p.sig247 = -247.0 * p.sig;
+    p.k64e = 6.4 * p.eta;
     return p;
   }
 
@@ -245,16 +255,49 @@ struct SpinPrec {
     w.k9 = 6.4 * v6 * w.v3;  // (32/5) v^9
     w.r = fast_rcp(w.k9 * p.eta * w.poly);
   }
+  // The right-hand side itself: the expressions of forward() with the
+  // constant factors folded into prepared coefficients (-3 S_j, -3 q S1,
+  // 721 sig, (32/5) eta) and v^6/2 into the two precession coefficients, so
+  // that each multiply of a constant by a product is done once per
+  // trajectory instead of once per evaluation; the same function up to
+  // rounding.  The adjoint differentiates forward().
   template <class T>
   __device__ static void f(double v, const T (&y)[D], const ParT<T>& p, T (&dy)[D]) {
-    FwdT<T> w;
-    forward(v, y, p, w);
-    const T cl = -v * p.ieta * w.r;
+    const double v2 = v * v;
+    const double v3 = v2 * v;
+    const double v4 = v2 * v2;
+    const double v6 = v3 * v3;
+    const double v6h = 0.5 * v6;
+    const T L = p.eta * fast_rcp(v);
+    const T Ls1 = fma(y[2], y[5], fma(y[1], y[4], y[0] * y[3]));
+    const T Ls2 = fma(y[2], y[8], fma(y[1], y[7], y[0] * y[6]));
+    const T s12 = fma(y[5], y[8], fma(y[4], y[7], y[3] * y[6]));
+    const T cL1 = fma(p.cq1, L, fma(p.m3S2, Ls2, p.m3qS1 * Ls1));
+    const T cL2 = fma(p.cq2, L, fma(p.m3S1, Ls1, p.m3iqS2 * Ls2));
+    const T A1 = v6h * cL1, B1 = v6h * p.S2;
+    const T A2 = v6h * cL2, B2 = v6h * p.S1;
+    T Om1[3], Om2[3], ds1[3], ds2[3];
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
-      dy[i] = cl * w.u[i];
-      dy[3 + i] = w.ds1[i] * w.r;
-      dy[6 + i] = w.ds2[i] * w.r;
+      Om1[i] = fma(A1, y[i], B1 * y[6 + i]);
+      Om2[i] = fma(A2, y[i], B2 * y[3 + i]);
+    }
+    ds1[0] = fma(Om1[1], y[5], -(Om1[2] * y[4]));
+    ds1[1] = fma(Om1[2], y[3], -(Om1[0] * y[5]));
+    ds1[2] = fma(Om1[0], y[4], -(Om1[1] * y[3]));
+    ds2[0] = fma(Om2[1], y[8], -(Om2[2] * y[7]));
+    ds2[1] = fma(Om2[2], y[6], -(Om2[0] * y[8]));
+    ds2[2] = fma(Om2[0], y[7], -(Om2[1] * y[6]));
+    const T beta = fma(p.c1, Ls1, p.c2 * Ls2);
+    const T sigma = fma(p.sig721 * Ls1, Ls2, p.sig247 * s12);
+    const T poly = fma(p.b4c + sigma, v4, fma(4.0 * M_PI - beta, v3, fma(p.b2, v2, 1.0)));
+    const T r = fast_rcp((p.k64e * (v6 * v3)) * poly);
+    const T cl = -v * p.ieta * r;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      dy[i] = cl * fma(p.S1, ds1[i], p.S2 * ds2[i]);
+      dy[3 + i] = ds1[i] * r;
+      dy[6 + i] = ds2[i] * r;
     }
   }
   __device__ static void vjp(double v, const double (&y)[D], const double (&th)[P], const Par& p,
