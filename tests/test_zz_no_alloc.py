@@ -101,3 +101,21 @@ def test_noalloc_size_limit_and_deferred_outputs():
     assert api.lib().gs_solve_noalloc(C.byref(s.args)) == 6   # GS_ERR_TOO_LARGE
     torch.cuda.synchronize()
     assert bool((s.status == -7).all())                       # nothing ran
+
+
+@pytest.mark.parametrize("tab", ["dopri5", "tsit5"])
+def test_noalloc_polynomial_outputs_in_the_loop(tab):
+    """Dopri5 and Tsit5 outputs whose deferred records would not fit the
+    static buffer are evaluated inside the solve kernel, on single lanes and
+    on 16-lane groups, in both output layouts: bitwise what gs_solve gives
+    by taking the steps again after the solve; small enough, they are
+    deferred in the buffer as in gs_solve."""
+    w = {**inputs.orbits_forward(n=400, seed=96), "tableau": tab}
+    for L in (api.Launch(), api.Launch(wide=400), api.Launch(wide=100, out_layout="knd")):
+        ref, out = _pair(w, L)     # (2 + 6) * 64 * 400 doubles: far beyond 4 KiB
+        _same(ref, out)
+        assert bool((out.status == 0).all())
+    small = {**inputs.orbits_forward(n=5, seed=97), "tableau": tab,
+             "t_out": np.linspace(5.0, 50.0, 10)}
+    ref, out = _pair(small, api.Launch(wide=2))   # 256 + 8 * 10 * 5 * 8 bytes: fits
+    _same(ref, out)
