@@ -765,30 +765,34 @@ __device__ __forceinline__ Attempt group_attempt(const Params& P, const GroupCoe
   }
   a.h_used = hh;
   double yn = 0.0;
-  sfor<S - 1>([&](auto J1) {
-    constexpr int j = decltype(J1)::value + 1;
-    double acc = 0.0;
-    sfor<j>([&](auto L) {
-      constexpr int l = decltype(L)::value;
-      if constexpr (TB::A(j, l) != 0.0) acc = fma(cf.a[j][l], s.k[l], acc);
-    });
-    const double Yc = fma(hh, acc, s.y);
-    s.k[j] = RowRhs<F>::f(s.t + cf.template node<j>() * hh, Yc, s.in.par, c);
-    if constexpr (TB::FSAL && j == S - 1) yn = Yc;
-  });
-  if constexpr (!TB::FSAL) {
-    double acc = 0.0;
+  // The sums over stages in push form: as soon as k_l is known its terms
+  // enter the partial sums of every later stage, of the update and of the
+  // error estimate.  Each sum still takes its terms in ascending l, as the
+  // single-lane attempt does, so the values are the same bit for bit; what
+  // changes is that only a_{j,j-1} k_{j-1} and the step stand between one
+  // stage's right-hand side and the next stage point, and the other terms
+  // fill the latency of the evaluation in flight.
+  double accs[S], accb = 0.0, e = 0.0;
+#pragma unroll
+  for (int j = 0; j < S; ++j) accs[j] = 0.0;
+  auto push = [&](auto L) {
+    constexpr int l = decltype(L)::value;
     sfor<S>([&](auto J) {
       constexpr int j = decltype(J)::value;
-      if constexpr (TB::B(j) != 0.0) acc = fma(cf.b[j], s.k[j], acc);
+      if constexpr (j > l && TB::A(j, l) != 0.0) accs[j] = fma(cf.a[j][l], s.k[l], accs[j]);
     });
-    yn = fma(hh, acc, s.y);
-  }
-  double e = 0.0;
-  sfor<S>([&](auto J) {
-    constexpr int j = decltype(J)::value;
-    if constexpr (TB::E(j) != 0.0) e = fma(cf.e[j], s.k[j], e);
+    if constexpr (!TB::FSAL && TB::B(l) != 0.0) accb = fma(cf.b[l], s.k[l], accb);
+    if constexpr (TB::E(l) != 0.0) e = fma(cf.e[l], s.k[l], e);
+  };
+  push(std::integral_constant<int, 0>{});
+  sfor<S - 1>([&](auto J1) {
+    constexpr int j = decltype(J1)::value + 1;
+    const double Yc = fma(hh, accs[j], s.y);
+    s.k[j] = RowRhs<F>::f(s.t + cf.template node<j>() * hh, Yc, s.in.par, c);
+    if constexpr (TB::FSAL && j == S - 1) yn = Yc;
+    push(std::integral_constant<int, j>{});
   });
+  if constexpr (!TB::FSAL) yn = fma(hh, accb, s.y);
   e *= hh;
   const double sc = fma(s.in.rtol, dmax(fabs(s.y), fabs(yn)), s.in.atol);
   const double r = e * fast_rcp1(sc);
