@@ -257,10 +257,12 @@ struct SpinPrec {
   }
   // The right-hand side itself: the expressions of forward() with the
   // constant factors folded into prepared coefficients (-3 S_j, -3 q S1,
-  // 721 sig, (32/5) eta) and v^6/2 into the two precession coefficients, so
-  // that each multiply of a constant by a product is done once per
-  // trajectory instead of once per evaluation; the same function up to
-  // rounding.  The adjoint differentiates forward().
+  // 721 sig, (32/5) eta), and v^6/2 and the reciprocal r of dv/dt folded into
+  // the two precession coefficients (so the precession vectors, and with
+  // them the cross products, come out already divided by dv/dt): each
+  // multiply by a constant or a common factor is done once instead of once
+  // per product; the same function up to rounding.  The adjoint
+  // differentiates forward().
   template <class T>
   __device__ static void f(double v, const T (&y)[D], const ParT<T>& p, T (&dy)[D]) {
     const double v2 = v * v;
@@ -274,8 +276,13 @@ struct SpinPrec {
     const T s12 = fma(y[5], y[8], fma(y[4], y[7], y[3] * y[6]));
     const T cL1 = fma(p.cq1, L, fma(p.m3S2, Ls2, p.m3qS1 * Ls1));
     const T cL2 = fma(p.cq2, L, fma(p.m3S1, Ls1, p.m3iqS2 * Ls2));
-    const T A1 = v6h * cL1, B1 = v6h * p.S2;
-    const T A2 = v6h * cL2, B2 = v6h * p.S1;
+    const T beta = fma(p.c1, Ls1, p.c2 * Ls2);
+    const T sigma = fma(p.sig721 * Ls1, Ls2, p.sig247 * s12);
+    const T poly = fma(p.b4c + sigma, v4, fma(4.0 * M_PI - beta, v3, fma(p.b2, v2, 1.0)));
+    const T r = fast_rcp((p.k64e * (v6 * v3)) * poly);
+    const T gr = v6h * r;
+    const T A1 = gr * cL1, B1 = gr * p.S2;
+    const T A2 = gr * cL2, B2 = gr * p.S1;
     T Om1[3], Om2[3], ds1[3], ds2[3];
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
@@ -288,16 +295,12 @@ struct SpinPrec {
     ds2[0] = fma(Om2[1], y[8], -(Om2[2] * y[7]));
     ds2[1] = fma(Om2[2], y[6], -(Om2[0] * y[8]));
     ds2[2] = fma(Om2[0], y[7], -(Om2[1] * y[6]));
-    const T beta = fma(p.c1, Ls1, p.c2 * Ls2);
-    const T sigma = fma(p.sig721 * Ls1, Ls2, p.sig247 * s12);
-    const T poly = fma(p.b4c + sigma, v4, fma(4.0 * M_PI - beta, v3, fma(p.b2, v2, 1.0)));
-    const T r = fast_rcp((p.k64e * (v6 * v3)) * poly);
-    const T cl = -v * p.ieta * r;
+    const T cl = -v * p.ieta;
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
       dy[i] = cl * fma(p.S1, ds1[i], p.S2 * ds2[i]);
-      dy[3 + i] = ds1[i] * r;
-      dy[6 + i] = ds2[i] * r;
+      dy[3 + i] = ds1[i];
+      dy[6 + i] = ds2[i];
     }
   }
   __device__ static void vjp(double v, const double (&y)[D], const double (&th)[P], const Par& p,
