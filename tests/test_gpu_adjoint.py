@@ -232,13 +232,19 @@ def test_tape_overflow_is_reported(k, cap):
     np.testing.assert_array_equal(sol.y_final.cpu().numpy(), ref.y_final.cpu().numpy())
 
 
+@pytest.mark.parametrize("ordered", [False, True], ids=["index", "permuted"])
 @pytest.mark.parametrize("tab", ["tsit5", "verner7"])
 @pytest.mark.parametrize("taped", [0, 1, 7], ids=["untaped", "store", "ckpt7"])
-def test_dense_queries_match_oracle_nodes(orc, tab, taped):
+def test_dense_queries_match_oracle_nodes(orc, tab, taped, ordered):
+    """Dense queries from the tape (or a replay from t0), for trajectories
+    taken in index order and in a random queue order (a trajectory's tape
+    records then sit in the slot of its queue position, not its index)."""
     w = inputs.orbits_forward(n=200, seed=54)
     w = {**w, "tableau": tab, "t_out": None}
     prob = _problem(w)
-    sol = _solve_taped(prob, k=taped) if taped else api.solve(prob)
+    order = np.random.default_rng(15).permutation(200) if ordered else None
+    L = api.Launch(ckpt_every=taped, ckpt_capacity=4096) if taped else api.Launch()
+    sol = api.solve(prob, L, order=order)
     torch.cuda.synchronize()
     rng = np.random.default_rng(14)
     tq = np.sort(rng.uniform(0.0, 50.0, (9, 200)), axis=0)
@@ -247,7 +253,7 @@ def test_dense_queries_match_oracle_nodes(orc, tab, taped):
     yq = api.dense_eval(sol, tq).cpu().numpy()
     o = oracle_solve(orc, {**w, "t_out": tq})
     err = np.abs(yq - o["y_out"]) / np.maximum(np.abs(o["y_out"]), 1.0)
-    record(f"dense queries {tab} taped={taped}", err.max(), 1e-9)
+    record(f"dense queries {tab} taped={taped} ordered={ordered}", err.max(), 1e-9)
     assert err.max() < 1e-9, err.max()
 
 

@@ -336,6 +336,43 @@ def test_wide_groups_write_the_checkpoint_tape(tab):
             assert torch.equal(x, y)
 
 
+@pytest.mark.parametrize("k", [1, 4], ids=["store", "ckpt4"])
+def test_wide_groups_with_outputs_and_a_tape(k):
+    """Groups writing output nodes (deferred records) and a tape in the same
+    launch: outputs, tape bytes and gradients with output cotangents are
+    those of one lane per trajectory."""
+    n = 600
+    w = inputs.orbits_forward(n=n, seed=56)
+    w = {**w, "t_out": w["t_out"][::4]}
+    order = np.random.default_rng(57).permutation(n)
+    p = api.make_problem(w["rhs"], w["tableau"], w["y0"], w["theta"], w["t0"], w["t1"],
+                         w["rtol"], w["atol"], w["t_out"])
+    nmax = int(api.solve(p).n_accepted.max())
+    cap = nmax // k + 2
+    sols = []
+    for wide in (0, 200):
+        s = api.Solution(p, api.Launch(block=128, ckpt_every=k, ckpt_capacity=cap, wide=wide))
+        s.set_order(order)
+        s.workspace.zero_()
+        s.run()
+        sols.append(s)
+    torch.cuda.synchronize()
+    a, b = sols
+    for key in ("y_final", "y_out", "n_accepted", "n_rejected", "status"):
+        assert torch.equal(getattr(a, key), getattr(b, key)), key
+    rec = 2 + 6 if k == 1 else 3 + 2 * 6
+    tape_bytes = n * cap * rec * 8
+    assert torch.equal(a.workspace[256:256 + tape_bytes], b.workspace[256:256 + tape_bytes])
+    yo = torch.as_tensor(np.random.default_rng(58).normal(size=(1, 6, p.K, n)), device="cuda")
+    yf = torch.ones((1, 6, n), dtype=torch.float64, device="cuda")
+    ga = api.solve_vjp(a, ybar_final=yf, ybar_out=yo)
+    gb = api.solve_vjp(b, ybar_final=yf, ybar_out=yo)
+    torch.cuda.synchronize()
+    for x, y in zip(ga, gb):
+        assert torch.equal(x, y)
+    assert bool(torch.isfinite(ga[0]).all())
+
+
 def test_wide_groups_write_the_store_tape():
     """Groups with a store-mode tape: the tape bytes, results and statuses of
     one lane per trajectory, and the same adjoint gradients from it; with a
