@@ -141,6 +141,12 @@ struct VjpParams {
 __device__ __forceinline__ double node_time(const Params& P, int kk, int64_t i) {
   return P.t_out_stride ? P.t_out[(int64_t)kk * P.t_out_stride + i] : P.t_out[kk];
 }
+// Time of output node kk, or -infinity for kk < 0 (K >= 1): the load takes
+// node 0 there and a select picks the result, so no branch guards the load.
+__device__ __forceinline__ double node_time_or_ninf(const Params& P, int kk, int64_t i) {
+  const double t = node_time(P, kk < 0 ? 0 : kk, i);
+  return kk >= 0 ? t : -__builtin_inf();
+}
 
 // Per-trajectory inputs (theta and the constants derived from it in the
 // scalar type of the solve: double, or ad::Dual for sensitivities).
@@ -1646,7 +1652,6 @@ __global__ void __launch_bounds__(256) vjp_kernel(Params P, VjpParams V) {
   bool live = false, ok = false;
   bool queue_empty = false;  // wave-uniform
   int32_t N = 0, cseg = -1, kp = -1;
-  double t_kp = -__builtin_inf();  // time of output node kp, kept in a register
 
   auto gbar = [&](int r, int c, int kk) -> double {
     return (V.ybar_out && r < V.R)
@@ -1689,7 +1694,6 @@ __global__ void __launch_bounds__(256) vjp_kernel(Params P, VjpParams V) {
       for (int c = 0; c < NP; ++c) THB(r, c) = 0.0;
     }
     kp = P.K - 1;
-    if constexpr (NODES) t_kp = kp >= 0 ? node_time(P, kp, i) : -__builtin_inf();
     cseg = (N + kseg - 1) / kseg - 1;
     if (!ok || cseg < 0) finish();
   };
@@ -1848,15 +1852,21 @@ __global__ void __launch_bounds__(256) vjp_kernel(Params P, VjpParams V) {
       if constexpr (!NODES) {
         reverse_step<TB, F, R, NODES>(s.in, tn, hn, yn, lam, thb, false, no_seed, ysc, ys);
       } else {
+        // The time of node kp is read for every step rather than carried
+        // from the previous one: carried across the step's reverse pass, the
+        // value (written inside the divergent node search below) was spilled
+        // by the compiler in the join block ahead of the exec-mask restore,
+        // so lanes that skipped the search kept a stale time and never
+        // reversed their inner nodes.  The load hits the cache.
+        double t_kp = node_time_or_ninf(P, kp, idx);
         // Nodes at the end of the step read y+ itself.
-        // (node times are read from memory only when a node is passed)
         while (kp >= 0 && t_kp == t_new) {
 #pragma unroll
           for (int r = 0; r < R; ++r)
 #pragma unroll
             for (int c = 0; c < D; ++c) lam[r][c] += gbar(r, c, kp);
           --kp;
-          t_kp = kp >= 0 ? node_time(P, kp, idx) : -__builtin_inf();
+          t_kp = node_time_or_ninf(P, kp, idx);
         }
         // Nodes inside the step: indices kp, kp - 1, ..., k_lo + 1.
         int k_lo = kp;
@@ -1894,7 +1904,6 @@ __global__ void __launch_bounds__(256) vjp_kernel(Params P, VjpParams V) {
           };
           reverse_step<TB, F, R, NODES>(s.in, tn, hn, yn, lam, thb, any, seed, ysc, ys);
           kp = k_lo;
-          t_kp = t_lo;
         } else {
           // Shortened-step outputs: each is a full step of length sigma h
           // from y_n with its own stage points, so each takes a reverse pass
@@ -1925,7 +1934,6 @@ __global__ void __launch_bounds__(256) vjp_kernel(Params P, VjpParams V) {
               }
             kp -= has ? 1 : 0;
           } while (has);
-          t_kp = t_lo;  // kp == k_lo here
         }
       }
     }
