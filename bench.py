@@ -54,9 +54,10 @@ PEAK_FP64_VECTOR_TFLOPS = 78.6   # MI355X: 256 CU x 2.4 GHz x 128 FP64 flop/clk
 #   and clipping 5, and one right-hand side per new stage (s - 1 for FSAL pairs, s else).
 #   Tsit5 + log halo (d 6, nnz(A) 21, nnz(e) 7, 13 per evaluation): 324 + 12 + 90 + 32 + 5
 #   + 78 = 541.  Dopri5 + log halo (nnz(A) 20, nnz(e) 6): 312 + 12 + 78 + 32 + 5 + 78 = 517.
-#   Verner 7 + precession (d 9, s 10, nnz(A) 36, nnz(b) 7, nnz(e) 8, 119 per evaluation):
-#   810 + 144 + 18 + 153 + 47 + 5 + 1190 = 2367; one output node (a shortened step) adds
-#   9 evaluations and the stage sums and update, 1071 + 810 + 144 = 2025.
+#   Verner 7 + precession (d 9, s 10, nnz(A) 36, nnz(b) 7, nnz(e) 8, 119 per evaluation of
+#   the unfolded right-hand side, the form the adjoint differentiates; the solve's folded
+#   form issues 97): 810 + 144 + 18 + 153 + 47 + 5 + 1190 = 2367; one output node (a
+#   shortened step) adds 9 evaluations and the stage sums and update, 1071 + 810 + 144 = 2025.
 FLOPS_PER_ATTEMPT = {("tsit5", "loghalo"): 541, ("dopri5", "loghalo"): 517,
                      ("verner7", "spinprec"): 2367}
 FLOPS_PER_NODE = {("verner7", "spinprec"): 2025, ("dopri5", "loghalo"): 168}

@@ -4,8 +4,13 @@ oracle's own tableaux: stage sums 2 d (nnz(A) + s - 1), the update of a
 non-FSAL pair 2 d (nnz(b) + 1), stage times 2 (s - 1), error weights
 2 d nnz(b - bhat) + d, norm 5 d + 2, controller 5, and F_f per new stage;
 per output node a polynomial evaluation or a shortened step.
-F_f is the hand count of each right-hand side as the kernels evaluate it
-(13 for the log halo, 119 for precession)."""
+F_f is the hand count of each right-hand side in its unfolded form, with
+products of parameters alone taken once per trajectory: 13 for the log halo;
+119 for precession, the form the adjoint differentiates (SpinPrec::forward and
+the products that turn it into dy).  The precession solve evaluates a folded
+form of the same function with 97 (the reciprocal of dv/dt folded into the
+precession coefficients, eta into the prepared coefficients), so its achieved
+rate counts the unfolded work."""
 import numpy as np
 
 import bench
