@@ -327,7 +327,9 @@ gs_status gs_solve_vjp(const gs_solve_args* fwd, const gs_vjp_args* vjp);
  * S_final [d][M][n] and, when K > 0, S_out [d][M][K][n]: S[c][m] is
  * d y_c / d input_m; for shared theta (theta_stride 0) it is the derivative
  * of each trajectory with respect to the shared value.  Columns run two per
- * launch.  No tape, no wide groups, queue schedule only.  1 <= M <= 16. */
+ * launch.  No tape; queue schedule only.  `wide` runs the head of the order
+ * on 16-lane groups as for gs_solve, values and tangents bit-identical to
+ * one lane per trajectory.  1 <= M <= 16. */
 typedef struct gs_sens_args {
   int32_t M;
   const int32_t* cols;    /* [M], host memory                              */

@@ -582,16 +582,21 @@ void sens_launches(const gs_solve_args* a, const gs_sens_args* sa) {
     S.m0 = m0;
     for (int m = 0; m < 4; ++m) S.col[m] = m < mm ? sa->cols[m0 + m] : -1;
     const int64_t need = (a->n + block - 1) / block;
-    int grid = a->grid > 0 ? (int)std::min<int64_t>(a->grid, need) : 0;
-    if (grid == 0) {
+    int64_t limit = a->grid;
+    if (a->grid <= 0) {
       int per_cu = 0;
       S.occupancy_out = &per_cu;
       ops(a->rhs, a->tableau).sens(P, S, mm, 0, block, s);
       S.occupancy_out = nullptr;
-      grid = (int)std::min<int64_t>((int64_t)std::max(per_cu, 1) * num_cus(), need);
+      limit = (int64_t)std::max(per_cu, 1) * num_cus();
     }
-    hipLaunchKernelGGL(reset_queues_kernel, dim3(1), dim3(64), 0, s, P.counters, 0ll);
-    ops(a->rhs, a->tableau).sens(P, S, mm, grid, block, s);
+    // The head of the order on 16-lane groups, as in a plain solve.
+    Params P2 = P;
+    int grid = (int)std::min<int64_t>(limit, need);
+    if (P.n_wide > 0) wide_split(P.n, P.n_wide, block, limit, &P2.wide_blocks, &grid);
+    hipLaunchKernelGGL(reset_queues_kernel, dim3(1), dim3(64), 0, s, P.counters,
+                       (long long)P.n_wide);
+    ops(a->rhs, a->tableau).sens(P2, S, mm, grid, block, s);
   }
 }
 
@@ -647,7 +652,7 @@ gs_status gs_solve_sens(const gs_solve_args* a, const gs_sens_args* sa) {
   if (st != GS_OK) return st;
   if (!sa || sa->M < 1 || sa->M > kSensMaxCols || !sa->cols || !sa->S_final) return GS_ERR_INVALID;
   if (a->K > 0 && !sa->S_out) return GS_ERR_INVALID;
-  if (is_stiff(a) || a->ckpt_every > 0 || a->wide > 0 || a->schedule != GS_SCHED_QUEUE)
+  if (is_stiff(a) || a->ckpt_every > 0 || a->schedule != GS_SCHED_QUEUE)
     return GS_ERR_UNSUPPORTED;
   for (int m = 0; m < sa->M; ++m)
     if (sa->cols[m] < 0 || sa->cols[m] >= a->d + a->p) return GS_ERR_INVALID;

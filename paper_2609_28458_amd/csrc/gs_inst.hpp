@@ -69,21 +69,34 @@ void launch_dense(const gs::Params& P, int32_t Q, const double* tq, double* yq, 
   hipLaunchKernelGGL((gs::dense_kernel<TB, F>), dim3(grid), dim3(block), 0, s, P, Q, tq, yq);
 }
 
-template <class TB, class F, int M>
-void launch_sens_m(const gs::Params& P, const gs::SensParams& S, int grid, int block,
+template <class TB, class F, int M, bool NODES, bool WIDE>
+void launch_sens_v(const gs::Params& P, const gs::SensParams& S, int grid, int block,
                    hipStream_t s) {
-  const void* fn = P.K > 0 ? reinterpret_cast<const void*>(&gs::sens_kernel<TB, F, M, true>)
-                           : reinterpret_cast<const void*>(&gs::sens_kernel<TB, F, M, false>);
+  const void* fn = reinterpret_cast<const void*>(&gs::sens_kernel<TB, F, M, NODES, WIDE>);
   if (grid <= 0) {
     int per_cu = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, block, 0) != hipSuccess) per_cu = 0;
     *S.occupancy_out = per_cu;
     return;
   }
-  if (P.K > 0)
-    hipLaunchKernelGGL((gs::sens_kernel<TB, F, M, true>), dim3(grid), dim3(block), 0, s, P, S);
-  else
-    hipLaunchKernelGGL((gs::sens_kernel<TB, F, M, false>), dim3(grid), dim3(block), 0, s, P, S);
+  hipLaunchKernelGGL((gs::sens_kernel<TB, F, M, NODES, WIDE>), dim3(grid), dim3(block), 0, s, P,
+                     S);
+}
+
+template <class TB, class F, int M>
+void launch_sens_m(const gs::Params& P, const gs::SensParams& S, int grid, int block,
+                   hipStream_t s) {
+  if (P.K > 0) {
+    if (P.n_wide > 0)
+      launch_sens_v<TB, F, M, true, true>(P, S, grid, block, s);
+    else
+      launch_sens_v<TB, F, M, true, false>(P, S, grid, block, s);
+  } else {
+    if (P.n_wide > 0)
+      launch_sens_v<TB, F, M, false, true>(P, S, grid, block, s);
+    else
+      launch_sens_v<TB, F, M, false, false>(P, S, grid, block, s);
+  }
 }
 
 template <class TB, class F>

@@ -599,6 +599,46 @@ struct FwdOccupancy {
 };
 
 
+// Sensitivity columns of a forward-mode solve (eq:sens, eq:stage-sens):
+// column m seeds the initial-condition component col[m] (< d) or the
+// parameter col[m] - d; tangents of every output land in S_final
+// [d][M][n] and S_out [d][M][K][n].  Step control reads values only, so the
+// steps are those of the plain solve.
+struct SensParams {
+  int32_t col[4];      // this launch's columns (template M of them)
+  int32_t m_total;     // columns of the output arrays
+  int32_t m0;          // first output column of this launch
+  double* S_final;
+  double* S_out;
+  int* occupancy_out;  // host-side, for the launcher's occupancy query only
+};
+
+// Seeded dual inputs: column m is the derivative with respect to
+// y0[col[m]] (col[m] < d) or theta[col[m] - d]; par is prepared from the
+// seeded theta so it carries d par / d theta.
+template <class F, int M>
+__device__ __forceinline__ void seed_inputs(const SensParams& SP, const Inputs<F>& ind,
+                                            const double (&y0)[F::D], Inputs<F, ad::Dual<M>>& in,
+                                            ad::Dual<M> (&y)[F::D]) {
+#pragma unroll
+  for (int c = 0; c < F::D; ++c) {
+    y[c].v = y0[c];
+#pragma unroll
+    for (int m = 0; m < M; ++m) y[c].d[m] = SP.col[m] == c ? 1.0 : 0.0;
+  }
+#pragma unroll
+  for (int q = 0; q < F::P; ++q) {
+    in.th[q].v = ind.th[q];
+#pragma unroll
+    for (int m = 0; m < M; ++m) in.th[q].d[m] = SP.col[m] == F::D + q ? 1.0 : 0.0;
+  }
+  in.par = F::prep(in.th);
+  in.t0 = ind.t0;
+  in.t1 = ind.t1;
+  in.rtol = ind.rtol;
+  in.atol = ind.atol;
+}
+
 // ---------------------------------------------------------------------------
 // Group mode: one trajectory on a group of 16 lanes (a DPP row), lane c of
 // the group holding component c of the state and of every stage.  Stage
@@ -629,6 +669,15 @@ __device__ __forceinline__ double row_bcast(double v) {
   return __longlong_as_double(
       __builtin_amdgcn_mov_dpp(__double_as_longlong(v), 0x150 + SRC, 0xF, 0xF, true));
 }
+// The same for a dual number: the value and each tangent.
+template <int SRC, int M>
+__device__ __forceinline__ ad::Dual<M> row_bcast(const ad::Dual<M>& v) {
+  ad::Dual<M> r;
+  r.v = row_bcast<SRC>(v.v);
+#pragma unroll
+  for (int m = 0; m < M; ++m) r.d[m] = row_bcast<SRC>(v.d[m]);
+  return r;
+}
 // Sum of lanes 0..D-1 of the row, in every lane of the row: each value is
 // broadcast and the sum taken in the pairwise order of error_norm2 (pairs,
 // then pairs of pairs, ...), so a group's norm has the bits of one lane's.
@@ -648,8 +697,8 @@ __device__ __forceinline__ double row_sum(double v) {
 }
 
 // Full vector of the row's components (lanes 0..D-1), in every lane.
-template <int D>
-__device__ __forceinline__ void row_gather(double v, double (&out)[D]) {
+template <int D, class T>
+__device__ __forceinline__ void row_gather(const T& v, T (&out)[D]) {
   sfor<D>([&](auto C) {
     constexpr int c = decltype(C)::value;
     out[c] = row_bcast<c>(v);
@@ -667,6 +716,21 @@ __device__ __forceinline__ double pick(const double (&v)[D], int c) {
     r = (r & ~m) | ((unsigned long long)__double_as_longlong(v[j]) & m);
   }
   return __longlong_as_double((long long)r);
+}
+template <int D, int M>
+__device__ __forceinline__ ad::Dual<M> pick(const ad::Dual<M> (&v)[D], int c) {
+  double part[D];
+  ad::Dual<M> r;
+#pragma unroll
+  for (int j = 0; j < D; ++j) part[j] = v[j].v;
+  r.v = pick<D>(part, c);
+#pragma unroll
+  for (int m = 0; m < M; ++m) {
+#pragma unroll
+    for (int j = 0; j < D; ++j) part[j] = v[j].d[m];
+    r.d[m] = pick<D>(part, c);
+  }
+  return r;
 }
 
 // Component c of f(t, Y) for the row whose lane c holds Y[c]: the full
@@ -703,6 +767,23 @@ struct RowRhs<LogHalo> {
     return c < 3 ? vel : s * (w * pos);
   }
 };
+
+// Component c of f for the solve's scalar type: the per-component form of
+// the row for double, and for dual numbers (sensitivity solves) the gathered
+// vector through the ordinary right-hand side, which is exactly the
+// arithmetic of one lane's sensitivity solve.
+template <class F, class T>
+__device__ __forceinline__ T row_f(double t, const T& yc,
+                                   const typename F::template ParT<T>& p, int c) {
+  if constexpr (std::is_same<T, double>::value) {
+    return RowRhs<F>::f(t, yc, p, c);
+  } else {
+    T Y[F::D], kf[F::D];
+    row_gather<F::D>(yc, Y);
+    F::f(t, Y, p, kf);
+    return c < F::D ? pick<F::D>(kf, c) : zero<T>();
+  }
+}
 
 // The tableau's coefficients in vector registers for the group loop.  As
 // immediates every 64-bit coefficient costs two scalar moves per use inside
@@ -742,12 +823,12 @@ struct GroupCoef {
   }
 };
 
-template <class TB, class F>
+template <class TB, class F, class T = double>
 struct GroupTraj {
   static constexpr int S = TB::S, D = F::D;
-  Inputs<F> in;
-  double y;     // own component (0 beyond d)
-  double k[S];  // own component of each stage derivative
+  Inputs<F, T> in;
+  T y;     // own component (0 beyond d)
+  T k[S];  // own component of each stage derivative
   double t, h, err_prev2;
   int32_t nacc, nrej, nanrun;
   int32_t ck_left;  // accepted steps until the next checkpoint
@@ -756,9 +837,9 @@ struct GroupTraj {
 // One attempt of a group: the single-lane attempt() component by component.
 // on_accept(t_old, h, y_old) runs on acceptance with the new state in s and
 // the step's stages still in s.k, as in the single-lane attempt.
-template <class TB, class F, class OnAccept>
+template <class TB, class F, class T, class OnAccept>
 __device__ __forceinline__ Attempt group_attempt(const Params& P, const GroupCoef<TB>& cf,
-                                                 GroupTraj<TB, F>& s, int c,
+                                                 GroupTraj<TB, F, T>& s, int c,
                                                  OnAccept&& on_accept) {
   constexpr int S = TB::S, D = F::D;
   Attempt a;
@@ -770,7 +851,7 @@ __device__ __forceinline__ Attempt group_attempt(const Params& P, const GroupCoe
     last = true;
   }
   a.h_used = hh;
-  double yn = 0.0;
+  T yn = zero<T>();
   // The sums over stages in push form: as soon as k_l is known its terms
   // enter the partial sums of every later stage, of the update and of the
   // error estimate.  Each sum still takes its terms in ascending l, as the
@@ -778,9 +859,10 @@ __device__ __forceinline__ Attempt group_attempt(const Params& P, const GroupCoe
   // changes is that only a_{j,j-1} k_{j-1} and the step stand between one
   // stage's right-hand side and the next stage point, and the other terms
   // fill the latency of the evaluation in flight.
-  double accs[S], accb = 0.0, e = 0.0;
+  T accs[S], accb = zero<T>();
+  double e = 0.0;  // the error estimate reads values only
 #pragma unroll
-  for (int j = 0; j < S; ++j) accs[j] = 0.0;
+  for (int j = 0; j < S; ++j) accs[j] = zero<T>();
   auto push = [&](auto L) {
     constexpr int l = decltype(L)::value;
     sfor<S>([&](auto J) {
@@ -788,19 +870,19 @@ __device__ __forceinline__ Attempt group_attempt(const Params& P, const GroupCoe
       if constexpr (j > l && TB::A(j, l) != 0.0) accs[j] = fma(cf.a[j][l], s.k[l], accs[j]);
     });
     if constexpr (!TB::FSAL && TB::B(l) != 0.0) accb = fma(cf.b[l], s.k[l], accb);
-    if constexpr (TB::E(l) != 0.0) e = fma(cf.e[l], s.k[l], e);
+    if constexpr (TB::E(l) != 0.0) e = fma(cf.e[l], ad::val(s.k[l]), e);
   };
   push(std::integral_constant<int, 0>{});
   sfor<S - 1>([&](auto J1) {
     constexpr int j = decltype(J1)::value + 1;
-    const double Yc = fma(hh, accs[j], s.y);
-    s.k[j] = RowRhs<F>::f(s.t + cf.template node<j>() * hh, Yc, s.in.par, c);
+    const T Yc = fma(hh, accs[j], s.y);
+    s.k[j] = row_f<F>(s.t + cf.template node<j>() * hh, Yc, s.in.par, c);
     if constexpr (TB::FSAL && j == S - 1) yn = Yc;
     push(std::integral_constant<int, j>{});
   });
   if constexpr (!TB::FSAL) yn = fma(hh, accb, s.y);
   e *= hh;
-  const double sc = fma(s.in.rtol, dmax(fabs(s.y), fabs(yn)), s.in.atol);
+  const double sc = fma(s.in.rtol, dmax(fabs(ad::val(s.y)), fabs(ad::val(yn))), s.in.atol);
   const double r = e * fast_rcp1(sc);
   const double en2 = row_sum<D>(r * r) * (1.0 / D);
   const bool finite = (en2 - en2) == 0.0;
@@ -809,15 +891,15 @@ __device__ __forceinline__ Attempt group_attempt(const Params& P, const GroupCoe
   a.accepted = acc;
   const double t_new = last ? s.in.t1 : s.t + hh;
   a.t_new = t_new;
-  const bool fin = row_sum<D>(fma(yn, 0.0, 0.0)) == 0.0;
-  const double y_old = s.y;
-  s.y = acc ? yn : s.y;
+  const bool fin = row_sum<D>(fma(ad::val(yn), 0.0, 0.0)) == 0.0;
+  const T y_old = s.y;
+  s.y = ad::select(acc, yn, s.y);
   s.t = acc ? t_new : s.t;
   if (acc) on_accept(a.t_start, hh, y_old);
   if constexpr (TB::FSAL) {
-    s.k[0] = acc ? s.k[S - 1] : s.k[0];
+    s.k[0] = ad::select(acc, s.k[S - 1], s.k[0]);
   } else {
-    s.k[0] = RowRhs<F>::f(s.t, s.y, s.in.par, c);
+    s.k[0] = row_f<F>(s.t, s.y, s.in.par, c);
   }
   s.err_prev2 = acc ? dmax(en2, 1e-8) : s.err_prev2;
   s.nacc += acc ? 1 : 0;
@@ -836,9 +918,9 @@ __device__ __forceinline__ Attempt group_attempt(const Params& P, const GroupCoe
 // Component of the dense output (eq:dense) of a pair with a dense
 // polynomial, for the group lane that holds this component: the expression
 // and order of dense_value, so the value is that of one lane.
-template <class TB>
-__device__ __forceinline__ double group_dense(double h, double sigma, double y_end,
-                                              const double (&k)[TB::S]) {
+template <class TB, class T>
+__device__ __forceinline__ T group_dense(double h, double sigma, const T& y_end,
+                                         const T (&k)[TB::S]) {
   constexpr int S = TB::S;
   double w[S];
   sfor<S>([&](auto J) {
@@ -850,10 +932,41 @@ __device__ __forceinline__ double group_dense(double h, double sigma, double y_e
     });
     w[j] = TB::B(j) - acc * sigma;
   });
-  double acc = 0.0;
+  T acc = zero<T>();
 #pragma unroll
   for (int j = 0; j < S; ++j) acc = fma(w[j], k[j], acc);
   return fma(-h, acc, y_end);
+}
+
+// Component of a shortened-step output (a pair without a dense
+// polynomial): the step of length hs from (t, y_start) with k[0] =
+// f(t, y_start), as rk_stages takes it for one lane (sums from zero in
+// ascending l, the tableau's own nodes), so the value is that of one lane.
+// Overwrites k[1..s-1], which an accepted step of a pair without FSAL no
+// longer needs.
+template <class TB, class F, class T>
+__device__ __forceinline__ T group_short_step(const typename F::template ParT<T>& par,
+                                              double t, double hs, const T& y_start,
+                                              T (&k)[TB::S], int c) {
+  constexpr int S = TB::S;
+  static_assert(!TB::FSAL, "shortened-step outputs reuse the stages of a pair without FSAL");
+  sfor<S - 1>([&](auto J1) {
+    constexpr int j = decltype(J1)::value + 1;
+    T acc = zero<T>();
+    sfor<j>([&](auto L) {
+      constexpr int l = decltype(L)::value;
+      constexpr double a = TB::A(j, l);
+      if constexpr (a != 0.0) acc = fma(a, k[l], acc);
+    });
+    k[j] = row_f<F>(t + TB::C(j) * hs, fma(hs, acc, y_start), par, c);
+  });
+  T acc = zero<T>();
+  sfor<S>([&](auto J) {
+    constexpr int j = decltype(J)::value;
+    constexpr double b = TB::B(j);
+    if constexpr (b != 0.0) acc = fma(b, k[j], acc);
+  });
+  return fma(hs, acc, y_start);
 }
 
 // The group part of a forward launch: workgroups [0, wide_blocks) take the
@@ -869,14 +982,17 @@ __device__ __forceinline__ double group_dense(double h, double sigma, double y_e
 // exact hits directly, the others as deferred records (lane 0 the step's
 // start time and length, lane c component c of its start state), or with
 // INLOOP (a pair with a dense polynomial, no pending array) the dense value.
-template <class TB, class F, bool NODES, bool TAPE, bool INLOOP>
-__device__ void solve_group(const Params& P) {
+template <class TB, class F, class T, bool NODES, bool TAPE, bool INLOOP>
+__device__ void solve_group(const Params& P, const SensParams& SP) {
   constexpr int D = F::D;
-  constexpr bool DEFER = NODES && !INLOOP;
+  constexpr bool SENS = !std::is_same<T, double>::value;
+  constexpr int M = ad::width<T>::value;
+  static_assert(!(SENS && TAPE), "sensitivity solves keep no tape");
+  constexpr bool DEFER = NODES && !INLOOP && !SENS;
   const int lane = threadIdx.x & 63;
   const int c = lane & (kGroup - 1);
   const int first = lane & ~(kGroup - 1);  // the group's lane 0
-  GroupTraj<TB, F> s;
+  GroupTraj<TB, F, T> s;
   GroupCoef<TB> cf;
   cf.load();
   int64_t idx = -1, ts = 0;  // trajectory and its tape slot
@@ -885,23 +1001,29 @@ __device__ void solve_group(const Params& P) {
   int kp = 0;                           // next output node
   double t_next = __builtin_inf();      // its time, kept in a register
 
-  auto put_node = [&](int kk, double v, double t_start = 0.0, double hs = 0.0) {
+  auto put_node = [&](int kk, const T& v, double t_start = 0.0, double hs = 0.0) {
     if constexpr (DEFER) {
       double* rec = P.pending + ((int64_t)kk * P.n + idx) * (2 + D);
       if (c == 0) rec[1] = hs;
       if (hs != 0.0) {
         if (c == 0) rec[0] = t_start;
-        if (c < D) rec[2 + c] = v;
+        if (c < D) rec[2 + c] = ad::val(v);
         return;
       }
     }
-    if (c < D)
+    if (c < D) {
       P.y_out[P.out_layout ? ((int64_t)kk * P.n + idx) * D + c
-                           : ((int64_t)c * P.K + kk) * P.n + idx] = v;
+                           : ((int64_t)c * P.K + kk) * P.n + idx] = ad::val(v);
+      if constexpr (SENS) {
+#pragma unroll
+        for (int m = 0; m < M; ++m)
+          SP.S_out[(((int64_t)c * SP.m_total + SP.m0 + m) * P.K + kk) * P.n + idx] = v.d[m];
+      }
+    }
   };
   auto put_record = [&](int n, double h_in) {
     double* r = P.tape + ((int64_t)ts * P.ckpt_cap + n) * store_record_len<F>();
-    if (c < D) r[2 + c] = s.y;
+    if (c < D) r[2 + c] = ad::val(s.y);
     if (c == 0) {
       r[0] = s.t;
       r[1] = h_in;
@@ -915,13 +1037,24 @@ __device__ void solve_group(const Params& P) {
       r[2] = s.err_prev2;
     }
     if (c < D) {
-      r[3 + c] = s.y;
-      r[3 + D + c] = s.k[0];
+      r[3 + c] = ad::val(s.y);
+      r[3 + D + c] = ad::val(s.k[0]);
     }
   };
   auto finish = [&](int32_t st) {
-    for (; NODES && kp < P.K; ++kp) put_node(kp, __builtin_nan(""));
-    if (c < D) P.y_final[(int64_t)c * P.n + idx] = s.y;
+    if constexpr (NODES) {
+      T nan_v = zero<T>();
+      set_all(nan_v, __builtin_nan(""));
+      for (; kp < P.K; ++kp) put_node(kp, nan_v);
+    }
+    if (c < D) {
+      P.y_final[(int64_t)c * P.n + idx] = ad::val(s.y);
+      if constexpr (SENS) {
+#pragma unroll
+        for (int m = 0; m < M; ++m)
+          SP.S_final[((int64_t)c * SP.m_total + SP.m0 + m) * P.n + idx] = s.y.d[m];
+      }
+    }
     if (c == 0) {
       P.n_acc[idx] = s.nacc;
       P.n_rej[idx] = s.nrej;
@@ -939,10 +1072,19 @@ __device__ void solve_group(const Params& P) {
     }
     s.nacc = s.nrej = s.nanrun = 0;
     s.err_prev2 = 1.0;
+    Inputs<F> ind;  // the double inputs (the starting-step rule reads values)
     double y0[D];
-    load_inputs<F>(P, i, s.in, y0);
+    load_inputs<F>(P, i, ind, y0);
+    T yv[D];  // the initial state, seeded for a sensitivity solve
+    if constexpr (SENS) {
+      seed_inputs<F, M>(SP, ind, y0, s.in, yv);
+    } else {
+      s.in = ind;
+#pragma unroll
+      for (int j = 0; j < D; ++j) yv[j] = y0[j];
+    }
     s.t = s.in.t0;
-    s.y = c < D ? pick<D>(y0, c) : 0.0;
+    s.y = c < D ? pick<D>(yv, c) : zero<T>();
     bool fin = true;
 #pragma unroll
     for (int j = 0; j < D; ++j) fin = fin && (y0[j] == y0[j]) && (fabs(y0[j]) < __builtin_inf());
@@ -965,10 +1107,13 @@ __device__ void solve_group(const Params& P) {
       finish(ST_OK);
       return;
     }
-    double f0[D];
-    F::f(s.t, y0, s.in.par, f0);
-    s.k[0] = c < D ? pick<D>(f0, c) : 0.0;
-    s.h = P.h0 > 0.0 ? dmin(P.h0, s.in.t1 - s.in.t0) : initial_step<TB, F>(s.in, y0, f0);
+    T f0[D];
+    double f0v[D];
+    F::f(s.t, yv, s.in.par, f0);
+#pragma unroll
+    for (int j = 0; j < D; ++j) f0v[j] = ad::val(f0[j]);
+    s.k[0] = c < D ? pick<D>(f0, c) : zero<T>();
+    s.h = P.h0 > 0.0 ? dmin(P.h0, s.in.t1 - s.in.t0) : initial_step<TB, F>(ind, y0, f0v);
     s.ck_left = P.ckpt_every;
     if constexpr (TAPE) {
       if (P.ckpt_cap <= 0)
@@ -1011,7 +1156,7 @@ __device__ void solve_group(const Params& P) {
           st = ST_MAX_STEPS;
         } else {
           const Attempt a = group_attempt<TB, F>(
-              P, cf, s, c, [&](double t_old, double hh, double y_old) {
+              P, cf, s, c, [&](double t_old, double hh, const T& y_old) {
                 if constexpr (!NODES) return;
                 while (t_next <= s.t) {
                   const double tq = t_next;
@@ -1022,6 +1167,9 @@ __device__ void solve_group(const Params& P) {
                              TB::POLY_DENSE ? hh : ((tq - t_old) / hh) * hh);
                   } else if constexpr (TB::POLY_DENSE) {
                     put_node(kp, group_dense<TB>(hh, (tq - t_old) / hh, s.y, s.k));
+                  } else {
+                    put_node(kp, group_short_step<TB, F>(s.in.par, t_old,
+                                                         ((tq - t_old) / hh) * hh, y_old, s.k, c));
                   }
                   ++kp;
                   t_next = kp < P.K ? node_time(P, kp, idx) : __builtin_inf();
@@ -1059,46 +1207,6 @@ __device__ void solve_group(const Params& P) {
 // NODES: the call has output nodes (K > 0); TAPE: it keeps a checkpoint
 // tape.  The host picks the variant, so a plain solve runs a loop with
 // neither check in it.
-// Sensitivity columns of a forward-mode solve (eq:sens, eq:stage-sens):
-// column m seeds the initial-condition component col[m] (< d) or the
-// parameter col[m] - d; tangents of every output land in S_final
-// [d][M][n] and S_out [d][M][K][n].  Step control reads values only, so the
-// steps are those of the plain solve.
-struct SensParams {
-  int32_t col[4];      // this launch's columns (template M of them)
-  int32_t m_total;     // columns of the output arrays
-  int32_t m0;          // first output column of this launch
-  double* S_final;
-  double* S_out;
-  int* occupancy_out;  // host-side, for the launcher's occupancy query only
-};
-
-// Seeded dual inputs: column m is the derivative with respect to
-// y0[col[m]] (col[m] < d) or theta[col[m] - d]; par is prepared from the
-// seeded theta so it carries d par / d theta.
-template <class F, int M>
-__device__ __forceinline__ void seed_inputs(const SensParams& SP, const Inputs<F>& ind,
-                                            const double (&y0)[F::D], Inputs<F, ad::Dual<M>>& in,
-                                            ad::Dual<M> (&y)[F::D]) {
-#pragma unroll
-  for (int c = 0; c < F::D; ++c) {
-    y[c].v = y0[c];
-#pragma unroll
-    for (int m = 0; m < M; ++m) y[c].d[m] = SP.col[m] == c ? 1.0 : 0.0;
-  }
-#pragma unroll
-  for (int q = 0; q < F::P; ++q) {
-    in.th[q].v = ind.th[q];
-#pragma unroll
-    for (int m = 0; m < M; ++m) in.th[q].d[m] = SP.col[m] == F::D + q ? 1.0 : 0.0;
-  }
-  in.par = F::prep(in.th);
-  in.t0 = ind.t0;
-  in.t1 = ind.t1;
-  in.rtol = ind.rtol;
-  in.atol = ind.atol;
-}
-
 // The forward solve for scalar type T (double, or ad::Dual<M> carrying M
 // sensitivity columns).  Persistent grid: each lane holds one trajectory;
 // when at least `refill` lanes of a wavefront are idle, one atomic fetches
@@ -1345,7 +1453,7 @@ __global__ void __launch_bounds__(256)
     __attribute__((amdgpu_waves_per_eu(FwdOccupancy<TB, F>::waves, 8))) solve_kernel(Params P) {
   if constexpr (F::D <= kGroup) {
     if ((int)blockIdx.x < P.wide_blocks) {  // uniform per workgroup
-      solve_group<TB, F, NODES, TAPE, INLOOP>(P);
+      solve_group<TB, F, double, NODES, TAPE, INLOOP>(P, SensParams{});
       return;
     }
   }
@@ -1394,9 +1502,17 @@ __global__ void __launch_bounds__(256) short_step_kernel(Params P) {
     P.y_out[P.out_layout ? (kk * P.n + i) * D + c : ((int64_t)c * P.K + kk) * P.n + i] = out[c];
 }
 
-// Forward solve with M sensitivity columns in the same launch.
-template <class TB, class F, int M, bool NODES>
+// Forward solve with M sensitivity columns in the same launch.  WIDE: the
+// launch runs the head of the order on 16-lane groups (a variant of its own,
+// so that a launch without groups keeps the single-lane register budget).
+template <class TB, class F, int M, bool NODES, bool WIDE>
 __global__ void __launch_bounds__(256) sens_kernel(Params P, SensParams SP) {
+  if constexpr (WIDE && F::D <= kGroup) {
+    if ((int)blockIdx.x < P.wide_blocks) {  // uniform per workgroup
+      solve_group<TB, F, ad::Dual<M>, NODES, false, false>(P, SP);
+      return;
+    }
+  }
   forward_body<TB, F, ad::Dual<M>, NODES, false>(P, SP);
 }
 

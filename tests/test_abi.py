@@ -150,9 +150,9 @@ def test_sens_argument_checks():
     assert api.lib().gs_solve_sens(C.byref(a), C.byref(api.gs_sens_args(0, C.cast(cols, C.c_void_p), 0x1000, 0))) == 1
     bad = (C.c_int32 * 2)(0, 9)  # d + p = 9 columns exist
     assert api.lib().gs_solve_sens(C.byref(a), C.byref(api.gs_sens_args(2, C.cast(bad, C.c_void_p), 0x1000, 0))) == 1
-    # no tape and no wide groups with sensitivities
+    # no tape with sensitivities; wide groups need the queue schedule
     assert api.lib().gs_solve_sens(C.byref(_args(ckpt_every=4, ckpt_capacity=10)), C.byref(ok)) == 2
-    assert api.lib().gs_solve_sens(C.byref(_args(wide=8)), C.byref(ok)) == 2
+    assert api.lib().gs_solve_sens(C.byref(_args(wide=8, schedule=1)), C.byref(ok)) == 2
 
 
 def _de_args(**kw):

@@ -5,6 +5,8 @@ The solution is the plain solve's, bit for bit (step control reads values
 only); the tangents are the oracle's forward sensitivities of the same
 discrete solution, at the output nodes and at t1, up to rounding.
 """
+import dataclasses
+
 import numpy as np
 import pytest
 
@@ -55,6 +57,54 @@ def test_sensitivities_match_oracle(orc, name, make, tab):
     if S_out is not None:
         _close(S_out.cpu().numpy(), o["S_out"])
 
+
+
+def _same_sens(prob, cols, launch, order=None):
+    """Solution, outputs and tangents of `launch` against the same launch
+    with one lane per trajectory."""
+    ref, Sf, So = api.solve_sens(prob, cols, dataclasses.replace(launch, wide=0), order=order)
+    got, Gf, Go = api.solve_sens(prob, cols, launch, order=order)
+    torch.cuda.synchronize()
+    r, g = to_np(ref), to_np(got)
+    for k in r:
+        np.testing.assert_array_equal(g[k], r[k], err_msg=k)
+    np.testing.assert_array_equal(Gf.cpu().numpy(), Sf.cpu().numpy(), err_msg="S_final")
+    if So is not None:
+        np.testing.assert_array_equal(Go.cpu().numpy(), So.cpu().numpy(), err_msg="S_out")
+    return r
+
+
+@pytest.mark.parametrize("tab", ["dopri5", "tsit5", "verner7"])
+@pytest.mark.parametrize("name,make", CASES, ids=[c[0] for c in CASES])
+def test_wide_group_sensitivities_equal_single_lanes(name, make, tab):
+    """Sensitivities on 16-lane groups (the head of the queue, then every
+    trajectory), with output nodes and with the final state only: the
+    solution, the outputs and every tangent bitwise those of one lane per
+    trajectory (a group gathers its dual stage point and evaluates the
+    ordinary right-hand side; Verner 7 takes its shortened-step outputs on
+    the group)."""
+    w = {**make(150), "tableau": tab}
+    for ww in (w, {**w, "t_out": None}):
+        prob = _prob(ww)
+        d, p = prob.d, api.NPARAM[prob.rhs]
+        cols = [0, d + p - 1, d - 1]  # two launches, two columns then one
+        for wide in (37, prob.n):
+            r = _same_sens(prob, cols, api.Launch(wide=wide))
+        assert np.all(r["status"] == 0)
+
+
+@pytest.mark.parametrize("tab", ["dopri5", "verner7"])
+def test_wide_group_sensitivities_of_stopped_trajectories(tab):
+    """A step limit stops most trajectories: NaN outputs and tangents past
+    the stop, statuses and counts, bitwise those of one lane each; a
+    longest-first order puts the longest on the groups."""
+    w = {**inputs.orbits_forward(200, seed=55), "tableau": tab}
+    prob = _prob(w)
+    order = np.argsort(-inputs.predicted_cost(w), kind="stable")
+    for L in (dict(), dict(max_steps=120)):
+        r = _same_sens(prob, [6, 7], api.Launch(wide=64, **L), order=order)
+        if L:
+            assert np.any(r["status"] != 0)
 
 def test_sensitivities_of_the_gradient_workload(orc):
     """100,000 orbits to t = 100 with the two halo parameters (v0, q) as
