@@ -519,8 +519,10 @@ def c3_gradient(torch, api, inputs, autotune):
 
     def grad_ms(block, grid, k, order, wide=0, adj=None):
         """One gradient step: forward with tape (block, grid, wide), then the adjoint
-        (on the same shape, or on adj = (block, grid))."""
-        ab, ag = adj or (block, grid)
+        (on the same shape, or on adj = (block, grid, wide)); the adjoint's groups
+        need the store-mode tape (k = 1)."""
+        ab, ag, aw = adj or (block, grid, wide)
+        aw = aw if k == 1 else 0
         taped = api.Solution(pg, api.Launch(block=block, grid=grid, ckpt_every=k,
                                             ckpt_capacity=nmax // k + 2, wide=wide))
         if order is not None:
@@ -529,7 +531,7 @@ def c3_gradient(torch, api, inputs, autotune):
         def grad_step():
             taped.run()
             ybf[0, :3] = 2.0 * (taped.y_final[:3] - T)
-            api.solve_vjp(taped, ybar_final=ybf, block=ab, grid=ag)
+            api.solve_vjp(taped, ybar_final=ybf, block=ab, grid=ag, wide=aw)
 
         return timed(grad_step, reps, 1, torch)
 
@@ -552,22 +554,21 @@ def c3_gradient(torch, api, inputs, autotune):
                                          wide=wd))
         t1.set_order(o)
         fwd_alone[name] = round(timed(lambda: t1.run(), reps, 1, torch), 4)
-        if wd == 0:
-            ybf[0, :3] = 2.0 * (t1.y_final[:3] - T)
-            adj_alone[name] = round(timed(lambda: api.solve_vjp(t1, ybar_final=ybf, block=b,
-                                                                grid=g), reps, 1, torch), 4)
+        ybf[0, :3] = 2.0 * (t1.y_final[:3] - T)
+        adj_alone[name] = round(timed(lambda: api.solve_vjp(t1, ybar_final=ybf, block=b,
+                                                            grid=g, wide=wd), reps, 1, torch), 4)
         del t1
     fname = min(fwd_alone, key=fwd_alone.get)
     aname = min(adj_alone, key=adj_alone.get)
     fb, fg, fo, fw = shapes[fname]
-    ab, ag = shapes[aname][:2]
-    ms_split = round(grad_ms(fb, fg, 1, fo, fw, adj=(ab, ag)), 4)
+    ab, ag, _, aw = shapes[aname]
+    ms_split = round(grad_ms(fb, fg, 1, fo, fw, adj=(ab, ag, aw)), 4)
     split_name = f"forward: {fname}; adjoint: {aname}"
     by_shape[split_name] = ms_split
     shapes[split_name] = (fb, fg, fo, fw)
     gshape = min(by_shape, key=by_shape.get)
     gb, gg, go, gw = shapes[gshape]
-    gadj = (ab, ag) if gshape == split_name else (gb, gg)
+    gadj = (ab, ag, aw) if gshape == split_name else (gb, gg, gw)
     per_k = {1: by_shape[gshape]}
     for k in (8, 32, 128):
         per_k[k] = round(grad_ms(gb, gg, k, go, adj=gadj), 4)
@@ -587,8 +588,8 @@ def c3_gradient(torch, api, inputs, autotune):
     fused.run()
     ybf[0, :3] = 2.0 * (fused.y_final[:3] - T)
     steps_g = int(fused.n_accepted.to(torch.int64).sum())
-    ms_vjp = timed(lambda: api.solve_vjp(fused, ybar_final=ybf, block=gadj[0], grid=gadj[1]),
-                   reps, 1, torch)
+    ms_vjp = timed(lambda: api.solve_vjp(fused, ybar_final=ybf, block=gadj[0], grid=gadj[1],
+                                         wide=gadj[2]), reps, 1, torch)
     fvs = FLOPS_PER_VJP_STEP[("dopri5", "loghalo")]
     ach_vjp = steps_g * fvs / (ms_vjp * 1e-3) / 1e12
     i_g = int(torch.argmax(fused.n_accepted))
@@ -597,6 +598,7 @@ def c3_gradient(torch, api, inputs, autotune):
     ms_f1 = timed(lambda: s1.run(), 3, 1, torch)
     yb1 = torch.ones((1, 6, 1), dtype=torch.float64, device="cuda")
     ms_v1 = timed(lambda: api.solve_vjp(s1, ybar_final=yb1), 3, 1, torch)
+    ms_v1g = timed(lambda: api.solve_vjp(s1, ybar_final=yb1, wide=1), 3, 1, torch)
     vjp_roofline = {"kernel": "gs::vjp_kernel<Dopri5, LogHalo>, store-mode tape",
                     "launch": aname if gshape == split_name else gshape, "bound": "alu",
                     "flops_per_accepted_step": fvs,
@@ -606,11 +608,13 @@ def c3_gradient(torch, api, inputs, autotune):
                     "critical_path": {
                         "max_accepted_one_orbit": int(fused.n_accepted.max()),
                         "longest_alone_ms": {"forward_with_tape": round(ms_f1, 3),
-                                             "adjoint": round(ms_v1, 3)},
+                                             "adjoint": round(ms_v1, 3),
+                                             "adjoint_on_a_group": round(ms_v1g, 3)},
                         "batch_adjoint_over_longest_alone": round(ms_vjp / ms_v1, 3)}}
     log(f"[bench] c3: forward {ms_fwd:.3f} ms, gradient {best[1]:.3f} ms ({gshape}, k = "
         f"{best[0]}), adjoint alone {ms_vjp:.3f} ms ({ach_vjp / PEAK_FP64_VECTOR_TFLOPS:.1%}), "
-        f"longest orbit's adjoint alone {ms_v1:.3f} ms")
+        f"longest orbit's adjoint alone {ms_v1:.3f} ms ({ms_v1g:.3f} ms on a group); "
+        f"alone by launch {adj_alone}")
     del fused, s1
     # forward sensitivities (the paper's own derivative), 2 and 9 columns, one
     # lane per orbit or the longest 256 on 16-lane groups (the batch is bound

@@ -231,6 +231,14 @@ typedef struct gs_vjp_args {
   int32_t block;            /* 0 = automatic                                */
   int32_t grid;             /* 0 = automatic                                */
   void* stream;             /* hipStream_t                                  */
+  int32_t wide;             /* the first `wide` positions of the queue order
+                               reversed on 16 lanes each (one component per
+                               lane), bitwise as one lane reverses them;
+                               store-mode tapes (ckpt_every 1) of losses on
+                               the final state only (K = 0), else
+                               GS_ERR_UNSUPPORTED.  0 = none.  The groups and
+                               the single lanes share the grid as for
+                               gs_solve's `wide`.                           */
 } gs_vjp_args;
 
 /* Fill a gs_solve_args with defaults: the paper's controller (safety 0.9,

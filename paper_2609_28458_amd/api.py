@@ -66,7 +66,7 @@ class gs_vjp_args(C.Structure):
     _fields_ = [
         ("R", C.c_int32), ("ybar_out", C.c_void_p), ("ybar_final", C.c_void_p),
         ("y0bar", C.c_void_p), ("thetabar", C.c_void_p), ("block", C.c_int32),
-        ("grid", C.c_int32), ("stream", C.c_void_p),
+        ("grid", C.c_int32), ("stream", C.c_void_p), ("wide", C.c_int32),
     ]
 
 
@@ -497,8 +497,11 @@ def de_profile(lam, omega_m, h, a0, omega_r, N_nodes, data, sigma, *, iters=20, 
     return out
 
 
-def solve_vjp(sol: Solution, ybar_final=None, ybar_out=None, block=0, grid=0, stream=None):
-    """Cotangents [R][d][n] / [R][d][K][n] -> (y0bar [R][d][n], thetabar [R][p][n])."""
+def solve_vjp(sol: Solution, ybar_final=None, ybar_out=None, block=0, grid=0, stream=None,
+              wide=0):
+    """Cotangents [R][d][n] / [R][d][K][n] -> (y0bar [R][d][n], thetabar [R][p][n]).
+    ``wide``: the head of the queue order reversed on 16-lane groups (store-mode
+    tape, final-state cotangents only)."""
     p = sol.prob
     dev = p.y0.device
     ref = ybar_final if ybar_final is not None else ybar_out
@@ -514,7 +517,7 @@ def solve_vjp(sol: Solution, ybar_final=None, ybar_out=None, block=0, grid=0, st
     y0bar = torch.empty((R, p.d, p.n), dtype=torch.float64, device=dev)
     thbar = torch.empty((R, NPARAM[p.rhs], p.n), dtype=torch.float64, device=dev)
     v = gs_vjp_args(R, _ptr(yo), _ptr(yf), _ptr(y0bar), _ptr(thbar), block, grid,
-                    _stream_handle(stream))
+                    _stream_handle(stream), int(wide))
     sol.args.stream = v.stream
     gs_solve_vjp(sol.args, v)
     return y0bar, thbar

@@ -38,6 +38,11 @@ constexpr int kSensMaxCols = 16;          // sensitivity columns per call
 __global__ void reset_counters_kernel(unsigned long long* c, int n) {
   if ((int)threadIdx.x < n) c[threadIdx.x] = 0ull;
 }
+// Adjoint queue heads: single lanes start after the head the groups reverse.
+__global__ void reset_vjp_queues_kernel(unsigned long long* c, long long n_wide) {
+  if (threadIdx.x == 0) c[1] = (unsigned long long)n_wide;
+  if (threadIdx.x == 1) c[3] = 0ull;
+}
 // Forward queue heads: single lanes start after the wide head of the order.
 __global__ void reset_queues_kernel(unsigned long long* c, long long n_wide) {
   if (threadIdx.x < 4) c[threadIdx.x] = threadIdx.x == 0 ? (unsigned long long)n_wide : 0ull;
@@ -510,6 +515,8 @@ gs_status gs_solve_vjp(const gs_solve_args* fwd, const gs_vjp_args* v) {
   if (fwd->ckpt_every <= 0) return GS_ERR_NO_TAPE;
   if (v->block != 0 && (v->block < 64 || v->block > 256 || v->block % 64 != 0))
     return GS_ERR_INVALID;
+  if (v->wide < 0) return GS_ERR_INVALID;
+  if (v->wide > 0 && (fwd->ckpt_every != 1 || fwd->K > 0)) return GS_ERR_UNSUPPORTED;
   if (fwd->n == 0) return GS_OK;
   const Layout L = layout_of(fwd);
   // The stage points of the step each lane reverses live in LDS, (s - 1) d
@@ -521,7 +528,9 @@ gs_status gs_solve_vjp(const gs_solve_args* fwd, const gs_vjp_args* v) {
   while (block > 64 && lds_lane * block > max_lds_per_block()) block -= 64;
   if (lds_lane * block > max_lds_per_block()) return GS_ERR_UNSUPPORTED;
   hipStream_t s = static_cast<hipStream_t>(v->stream);
-  const Params P = make_params(fwd);
+  Params P = make_params(fwd);
+  P.n_wide = std::min<int64_t>(v->wide, fwd->n);  // the adjoint's own groups
+  P.wide_blocks = 0;
   VjpParams V;
   std::memset(&V, 0, sizeof V);
   V.R = std::min(kVjpMaxR, (int)v->R);
@@ -539,6 +548,7 @@ gs_status gs_solve_vjp(const gs_solve_args* fwd, const gs_vjp_args* v) {
     if (per_cu > 0) grid = (int)std::min<int64_t>(grid, (int64_t)per_cu * num_cus());
   }
   if (grid < 1) return GS_ERR_INVALID;
+  if (P.n_wide > 0) wide_split(P.n, P.n_wide, block, grid, &P.wide_blocks, &grid);
   V.R_total = v->R;
   V.ybar_out = v->ybar_out;
   V.ybar_final = v->ybar_final;
@@ -555,7 +565,8 @@ gs_status gs_solve_vjp(const gs_solve_args* fwd, const gs_vjp_args* v) {
   for (int r0 = 0; r0 < v->R; r0 += kVjpMaxR) {
     V.r0 = r0;
     V.R = std::min(kVjpMaxR, v->R - r0);
-    hipLaunchKernelGGL(reset_counters_kernel, dim3(1), dim3(64), 0, s, P.counters + 1, 1);
+    hipLaunchKernelGGL(reset_vjp_queues_kernel, dim3(1), dim3(64), 0, s, P.counters,
+                       (long long)P.n_wide);
     ops(fwd->rhs, fwd->tableau).vjp(P, V, grid, block, s);
   }
   return hipGetLastError() == hipSuccess ? GS_OK : GS_ERR_HIP;

@@ -32,10 +32,10 @@ void launch_solve(const gs::Params& P, int grid, int block, hipStream_t s) {
   }
 }
 
-template <class TB, class F, bool NODES, bool STORE>
+template <class TB, class F, bool NODES, bool STORE, bool WIDE = false>
 void launch_vjp_r(const gs::Params& P, const gs::VjpParams& V, int grid, int block,
                   hipStream_t s) {
-  const void* fn = reinterpret_cast<const void*>(&gs::vjp_kernel<TB, F, 1, NODES, STORE>);
+  const void* fn = reinterpret_cast<const void*>(&gs::vjp_kernel<TB, F, 1, NODES, STORE, WIDE>);
   if (grid <= 0) {
     // Occupancy query: blocks per CU of the variant that would launch.
     int per_cu = 0;
@@ -44,10 +44,12 @@ void launch_vjp_r(const gs::Params& P, const gs::VjpParams& V, int grid, int blo
     *V.occupancy_out = per_cu;
     return;
   }
-  hipLaunchKernelGGL((gs::vjp_kernel<TB, F, 1, NODES, STORE>), dim3(grid), dim3(block), V.lds_bytes,
-                     s, P, V);
+  hipLaunchKernelGGL((gs::vjp_kernel<TB, F, 1, NODES, STORE, WIDE>), dim3(grid), dim3(block),
+                     V.lds_bytes, s, P, V);
 }
 
+// The head of the order runs on 16-lane groups (P.n_wide > 0) only for a
+// store-mode tape without output nodes; the host passes n_wide = 0 otherwise.
 template <class TB, class F>
 void launch_vjp(const gs::Params& P, const gs::VjpParams& V, int grid, int block, hipStream_t s) {
   if (P.K > 0) {
@@ -56,10 +58,14 @@ void launch_vjp(const gs::Params& P, const gs::VjpParams& V, int grid, int block
     else
       launch_vjp_r<TB, F, true, false>(P, V, grid, block, s);
   } else {
-    if (P.store)
-      launch_vjp_r<TB, F, false, true>(P, V, grid, block, s);
-    else
+    if (P.store) {
+      if (P.n_wide > 0)
+        launch_vjp_r<TB, F, false, true, true>(P, V, grid, block, s);
+      else
+        launch_vjp_r<TB, F, false, true>(P, V, grid, block, s);
+    } else {
       launch_vjp_r<TB, F, false, false>(P, V, grid, block, s);
+    }
   }
 }
 

@@ -1744,13 +1744,161 @@ struct RecBuf {
     return v[i / 2][i % 2];
   }
 };
-template <class TB, class F, int R, bool NODES, bool STORE>
+// Reverse of one step on a 16-lane group (one loss, no output seeds): the
+// single-lane reverse_step component by component.  Lane c holds component
+// c of the state, of the running cotangent and of every stage point and
+// stage cotangent; the right-hand side is evaluated per component (row_f)
+// and its vector-Jacobian product on the gathered stage point and stage
+// cotangent in every lane, which keeps its component of the result and
+// accumulates the same parameter cotangent as every other lane.  Sums run
+// in the single lane's order, so the cotangents are bitwise its own.
+template <class TB, class F>
+__device__ __forceinline__ void group_reverse_step(const GroupCoef<TB>& cf, const Inputs<F>& in,
+                                                   double t, double h, double yc, double& lam,
+                                                   double (&thb)[F::P], int c) {
+  constexpr int S = TB::S, D = F::D;
+  double Ys[S], k[S];
+#pragma unroll
+  for (int j = 0; j < S; ++j) Ys[j] = k[j] = 0.0;
+  Ys[0] = yc;
+  k[0] = row_f<F>(t, yc, in.par, c);
+  sfor<S - 1>([&](auto J1) {
+    constexpr int j = decltype(J1)::value + 1;
+    if constexpr (stage_feeds_step<TB>(j)) {
+      double acc = 0.0;
+      sfor<j>([&](auto L) {
+        constexpr int l = decltype(L)::value;
+        if constexpr (TB::A(j, l) != 0.0) acc = fma(cf.a[j][l], k[l], acc);
+      });
+      Ys[j] = fma(h, acc, yc);
+      if constexpr (j < S - 1) k[j] = row_f<F>(t + cf.template node<j>() * h, Ys[j], in.par, c);
+    }
+  });
+  double kb[S];
+  sfor<S>([&](auto J) {
+    constexpr int j = decltype(J)::value;
+    kb[j] = (h * TB::B(j)) * lam;
+  });
+  double yb = lam;
+  rfor<S>([&](auto J) {
+    constexpr int j = decltype(J)::value;
+    if constexpr (stage_feeds_step<TB>(j)) {
+      double Yf[D], kbf[D], ybf[D];
+      row_gather<D>(Ys[j], Yf);
+      row_gather<D>(kb[j], kbf);
+      F::vjp(t + TB::C(j) * h, Yf, in.th, in.par, kbf, ybf, thb);
+      const double ybj = c < D ? pick<D>(ybf, c) : 0.0;
+      yb += ybj;
+      sfor<j>([&](auto L) {
+        constexpr int l = decltype(L)::value;
+        constexpr double a = TB::A(j, l);
+        if constexpr (a != 0.0) kb[l] = fma(h * a, ybj, kb[l]);
+      });
+    }
+  });
+  lam = yb;
+}
+
+// The adjoint of the head of the queue order on 16-lane groups: one loss,
+// final-state cotangents, store-mode tape.  Groups take queue positions
+// [0, n_wide) from their own queue head (counters[3]), each walking its
+// trajectory's tape from the last accepted step to the first (record n
+// holds t_n and y_n, record n + 1 the length of step n) with the running
+// cotangents in registers; the single lanes take the rest.  Results are
+// written as one lane writes them: lane c component c of y0bar, lane 0 the
+// parameter cotangents.
+template <class TB, class F>
+__device__ void vjp_group(const Params& P, const VjpParams& V) {
+  constexpr int D = F::D, NP = F::P;
+  const int lane = threadIdx.x & 63;
+  const int c = lane & (kGroup - 1);
+  const int first = lane & ~(kGroup - 1);  // the group's lane 0
+  GroupCoef<TB> cf;
+  cf.load();
+  Inputs<F> in;
+  int64_t idx = -1, ts = 0;
+  bool live = false, ok = false, queue_empty = false;
+  int32_t n = -1;  // the step to reverse next
+  double lam = 0.0, thb[NP];
+#pragma unroll
+  for (int q = 0; q < NP; ++q) thb[q] = 0.0;
+  auto finish = [&]() {
+    if (c < D) V.y0bar[((int64_t)V.r0 * D + c) * P.n + idx] = ok ? lam : __builtin_nan("");
+    if (c == 0) {
+#pragma unroll
+      for (int q = 0; q < NP; ++q)
+        V.thetabar[((int64_t)V.r0 * NP + q) * P.n + idx] = ok ? thb[q] : __builtin_nan("");
+    }
+    live = false;
+  };
+  auto start = [&](int64_t i) {
+    idx = i;
+    live = true;
+    ok = P.status[i] == ST_OK;
+    ts = ok ? (int64_t)P.slot[i] : 0;
+    lam = (V.ybar_final && c < D && V.R > 0) ? V.ybar_final[((int64_t)V.r0 * D + c) * P.n + i]
+                                             : 0.0;
+#pragma unroll
+    for (int q = 0; q < NP; ++q) thb[q] = 0.0;
+    double y_unused[D];
+    load_inputs<F>(P, i, in, y_unused);
+    n = P.n_acc[i] - 1;
+    if (!ok || n < 0) finish();
+  };
+  for (;;) {
+    if (!queue_empty) {
+      const uint64_t idle = __ballot(!live && c == 0);  // one bit per idle group
+      const int nidle = __popcll(idle);
+      if (nidle > 0) {
+        unsigned long long base = 0;
+        if (lane == 0) base = atomicAdd(P.counters + 3, (unsigned long long)nidle);
+        base = first_lane(base);
+        if (base + (unsigned long long)nidle >= (unsigned long long)P.n_wide) queue_empty = true;
+        if (!live) {
+          const uint64_t below = first ? (~0ull >> (64 - first)) : 0ull;
+          const unsigned long long pos = base + __popcll(idle & below);
+          if (pos < (unsigned long long)P.n_wide) {
+            const int64_t id = P.order ? P.order[pos] : (int64_t)pos;
+            if (id >= 0 && id < P.n) start(id);
+          }
+        }
+      }
+    }
+    if (__ballot(live) == 0) {
+      if (queue_empty) break;
+      continue;
+    }
+    if (live) {
+      const double* rec = P.tape + ((int64_t)ts * P.ckpt_cap + n) * store_record_len<F>();
+      const double tn = rec[0];
+      const double hn = rec[store_record_len<F>() + 1];
+      const double yc = c < D ? rec[2 + c] : 0.0;
+      group_reverse_step<TB, F>(cf, in, tn, hn, yc, lam, thb, c);
+      --n;
+      if (n < 0) finish();
+    }
+  }
+}
+
+template <class TB, class F, int R, bool NODES, bool STORE, bool WIDE = false>
 __global__ void __launch_bounds__(256) vjp_kernel(Params P, VjpParams V) {
+  if constexpr (WIDE) {
+    static_assert(STORE && !NODES && R == 1 && F::D <= kGroup,
+                  "groups reverse store-mode tapes of final-state losses");
+    if ((int)blockIdx.x < P.wide_blocks) {  // uniform per workgroup
+      vjp_group<TB, F>(P, V);
+      return;
+    }
+  }
   constexpr int D = F::D, NP = F::P;
   constexpr int SREC = 2 + D;
   constexpr int AREC = D + NP;  // running cotangents of one loss
   const int lane = threadIdx.x & 63;
-  const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  // The per-wave scratch below is indexed from the first single-lane
+  // workgroup: the group workgroups use none, and the host sizes the grid's
+  // single-lane part, not the whole grid, to the scratch it has.
+  const int64_t wave =
+      (((int64_t)blockIdx.x - (WIDE ? P.wide_blocks : 0)) * blockDim.x + threadIdx.x) >> 6;
   constexpr bool store = STORE;
   // Steps per segment: the checkpoint interval, or in store mode a fixed
   // stretch of the tape (inputs, refill and bookkeeping once per segment).

@@ -126,6 +126,16 @@ def test_vjp_requires_tape():
     assert api.lib().gs_solve_vjp(C.byref(a), C.byref(v)) == 5
 
 
+
+def test_vjp_groups_need_a_store_tape_and_final_state_losses():
+    v = api.gs_vjp_args(1, None, 0x1000, 0x1000, 0x1000, 0, 0, None, -1)
+    store = dict(ckpt_every=1, ckpt_capacity=10)
+    assert api.lib().gs_solve_vjp(C.byref(_args(**store)), C.byref(v)) == 1
+    v.wide = 8
+    assert api.lib().gs_solve_vjp(C.byref(_args(ckpt_every=4, ckpt_capacity=10)), C.byref(v)) == 2
+    nodes = dict(K=3, t_out=0x1000, y_out=0x1000)
+    assert api.lib().gs_solve_vjp(C.byref(_args(**store, **nodes)), C.byref(v)) == 2
+
 def test_status_strings():
     for code in range(6):
         assert api.lib().gs_status_string(code)

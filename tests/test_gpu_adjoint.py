@@ -97,6 +97,56 @@ def test_vjp_matches_oracle_sensitivities(orc, name, make, tab, k, nodes):
     assert err.max() < VJP_BAR, (err.max(), np.unravel_index(err.argmax(), err.shape))
 
 
+
+@pytest.mark.parametrize("tab", ["dopri5", "tsit5", "verner7"])
+@pytest.mark.parametrize("name,make", CASES, ids=[c[0] for c in CASES])
+def test_wide_group_adjoint_equals_single_lanes(name, make, tab):
+    """The adjoint of a store-mode tape with the head of the queue (then every
+    trajectory) reversed on 16-lane groups, two losses: y0bar and thetabar
+    bitwise those of one lane per trajectory."""
+    w = {**make(150), "tableau": tab, "t_out": None}
+    prob = _problem(w)
+    sol = _solve_taped(prob, k=1, cap=20000)
+    assert np.all(sol.status.cpu().numpy() == 0)
+    ybf = np.random.default_rng(21).normal(size=(2, prob.d, prob.n))
+    ref = [x.cpu().numpy() for x in api.solve_vjp(sol, ybar_final=ybf)]
+    for wide in (37, prob.n):
+        got = [x.cpu().numpy() for x in api.solve_vjp(sol, ybar_final=ybf, wide=wide)]
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(got[0], ref[0], err_msg=f"y0bar wide={wide}")
+        np.testing.assert_array_equal(got[1], ref[1], err_msg=f"thetabar wide={wide}")
+
+
+def test_wide_group_adjoint_with_an_order_and_failed_trajectories():
+    """Longest first, the forward's own head on groups as well; a trajectory
+    with a non-finite start and one stopped by a small tape capacity get NaN
+    cotangents, bitwise as on one lane each."""
+    n = 400
+    w = {**inputs.orbits_forward(n, seed=57), "tableau": "dopri5", "t_out": None}
+    y0 = w["y0"].copy()
+    y0[1, 7] = np.nan
+    w = {**w, "y0": y0}
+    prob = _problem(w)
+    order = np.argsort(-inputs.predicted_cost(w), kind="stable")
+    plain = api.solve(prob)
+    torch.cuda.synchronize()
+    nmax = int(plain.n_accepted.max())
+    for fwide, cap in ((0, nmax + 2), (64, nmax + 2), (64, nmax // 2)):
+        sol = api.Solution(prob, api.Launch(ckpt_every=1, ckpt_capacity=cap, wide=fwide))
+        sol.set_order(order)
+        sol.run()
+        torch.cuda.synchronize()
+        st = sol.status.cpu().numpy()
+        assert st[7] != 0 and (cap > nmax or np.any(st == 4))
+        ybf = np.random.default_rng(22).normal(size=(1, prob.d, n))
+        ref = [x.cpu().numpy() for x in api.solve_vjp(sol, ybar_final=ybf)]
+        got = [x.cpu().numpy() for x in api.solve_vjp(sol, ybar_final=ybf, wide=96)]
+        torch.cuda.synchronize()
+        bad = st != 0
+        assert np.all(np.isnan(ref[0][:, :, bad])) and not np.any(np.isnan(ref[0][:, :, ~bad]))
+        np.testing.assert_array_equal(got[0], ref[0], err_msg=f"y0bar {fwide} {cap}")
+        np.testing.assert_array_equal(got[1], ref[1], err_msg=f"thetabar {fwide} {cap}")
+
 def test_checkpoint_interval_does_not_change_the_gradient():
     w = inputs.orbits_forward(n=200, seed=51)
     prob = _problem(w)
