@@ -10,6 +10,7 @@ import pytest
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
+from parity_log import allclose  # noqa: E402
 from paper_2609_28458_amd import api, inputs  # noqa: E402
 
 
@@ -65,10 +66,10 @@ def test_profile_matches_oracle(orc, spline):
     assert np.all(g["status"] == 0)
     for k in ("om", "h", "a0"):
         gk = g["omega_m" if k == "om" else k]
-        np.testing.assert_allclose(gk, o[k], rtol=1e-9, atol=0, err_msg=k)
-    np.testing.assert_allclose(g["chi2"], o["chi2"], rtol=1e-7, atol=1e-9)
-    np.testing.assert_allclose(g["dist"], o["dist"], rtol=1e-9, atol=0)
-    np.testing.assert_allclose(g["chi2_prev"], o["chi2_prev"], rtol=1e-7, atol=1e-9)
+        allclose(f"DE {k}", gk, o[k], rtol=1e-9)
+    allclose("DE chi2", g["chi2"], o["chi2"], rtol=1e-7, atol=1e-9)
+    allclose("DE distances", g["dist"], o["dist"], rtol=1e-9)
+    allclose("DE chi2 before the step", g["chi2_prev"], o["chi2_prev"], rtol=1e-7, atol=1e-9)
 
 
 def test_profile_recovers_noise_free_fiducial(orc):
@@ -114,9 +115,9 @@ def test_profile_full_size(orc, spline):
     assert abs(np.median(best) - w["fid"]["lam"]) < 0.3
     idx = np.random.default_rng(4).choice(10_000, 12, replace=False)
     o = _oracle(de, w, s, lam[idx], om[idx], h[idx], a0[idx], data[:, :, idx], sigma)
-    np.testing.assert_allclose(g["omega_m"][idx], o["om"], rtol=1e-9)
-    np.testing.assert_allclose(g["h"][idx], o["h"], rtol=1e-9)
-    np.testing.assert_allclose(g["chi2"][idx], o["chi2"], rtol=1e-7, atol=1e-9)
+    allclose("DE profile omega_m, sampled", g["omega_m"][idx], o["om"], rtol=1e-9)
+    allclose("DE profile h, sampled", g["h"][idx], o["h"], rtol=1e-9)
+    allclose("DE profile chi2, sampled", g["chi2"][idx], o["chi2"], rtol=1e-7, atol=1e-9)
 
 
 @pytest.mark.parametrize("kd", [1, 12], ids=["one_point", "two_chunks"])
@@ -146,6 +147,6 @@ def test_spline_data_counts(orc, kd):
     o = _oracle(de, w, s, lam, om, h, a0, data, sigma)
     assert np.all(g["status"] == 0)
     for k in ("om", "h", "a0"):
-        np.testing.assert_allclose(g["omega_m" if k == "om" else k], o[k], rtol=1e-9, err_msg=k)
-    np.testing.assert_allclose(g["chi2"], o["chi2"], rtol=1e-7, atol=1e-9)
-    np.testing.assert_allclose(g["dist"], o["dist"], rtol=1e-9, atol=0)
+        allclose(f"DE profile {k}", g["omega_m" if k == "om" else k], o[k], rtol=1e-9)
+    allclose("DE chi2", g["chi2"], o["chi2"], rtol=1e-7, atol=1e-9)
+    allclose("DE distances", g["dist"], o["dist"], rtol=1e-9)

@@ -14,6 +14,7 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 from gpu_util import gpu_solve, oracle_solve, to_np  # noqa: E402
+from parity_log import record  # noqa: E402
 from paper_2609_28458_amd import api, inputs  # noqa: E402
 from test_gpu_forward import CASES  # noqa: E402
 
@@ -30,10 +31,11 @@ def _prob(w):
                             w["rtol"], w["atol"], w.get("t_out"))
 
 
-def _close(got, ref, tol=1e-9):
+def _close(got, ref, tol=1e-9, name="sensitivities vs oracle"):
     # relative to the largest sensitivity of the trajectory (floor 1)
     scale = np.maximum(np.abs(ref).reshape(-1, ref.shape[-1]).max(axis=0), 1.0)
     err = np.abs(got - ref) / scale
+    record(name, err.max(), tol)
     assert err.max() < tol, err.max()
 
 
@@ -53,9 +55,9 @@ def test_sensitivities_match_oracle(orc, name, make, tab):
     assert np.all(g["status"] == 0)
     o = oracle_solve(orc, w, sens_cols=cols)
     np.testing.assert_array_equal(g["n_accepted"], o["n_accepted"])
-    _close(S_final.cpu().numpy(), o["S_final"])
+    _close(S_final.cpu().numpy(), o["S_final"], name=f"sens vs oracle {name} {tab} final")
     if S_out is not None:
-        _close(S_out.cpu().numpy(), o["S_out"])
+        _close(S_out.cpu().numpy(), o["S_out"], name=f"sens vs oracle {name} {tab} outputs")
 
 
 
@@ -118,4 +120,4 @@ def test_sensitivities_of_the_gradient_workload(orc):
     idx = np.sort(np.random.default_rng(21).choice(prob.n, 200, replace=False))
     o = oracle_solve(orc, w, idx, sens_cols=[6, 7])
     np.testing.assert_array_equal(sol.n_accepted.cpu().numpy()[idx], o["n_accepted"])
-    _close(S_final.cpu().numpy()[:, :, idx], o["S_final"])
+    _close(S_final.cpu().numpy()[:, :, idx], o["S_final"], name="sens vs oracle, gradient workload sample")
