@@ -587,19 +587,15 @@ __device__ __forceinline__ uint64_t lanemask_lt() {
 // least `refill` lanes of a wavefront are idle, one atomic fetches that many
 // queue positions and the idle lanes take them (ballot + prefix count).  In
 // static mode lane g integrates trajectory g and is never refilled.
-// Occupancy target of the forward kernel: two waves per SIMD.  The stage
-// array k[S][D] dominates the live registers; up to 63 doubles (126 VGPRs)
-// two waves fit in the 512-entry register file without spilling.  Verner 7
-// on the precession system (90 doubles) spills 330-470 bytes per lane at two
-// waves and still runs about 2% faster than at one, where it needs no
-// spill: the second wave fills the stalls of the first one's dependent
-// chains.
+// Occupancy target of the forward kernel: the stage array k[S][D] dominates
+// the live registers; up to 63 doubles (126 VGPRs) two waves per SIMD fit in
+// the 512-entry register file without spilling, beyond that one.
 #ifndef GS_FWD_WAVES
 #define GS_FWD_WAVES 2
 #endif
 template <class TB, class F>
 struct FwdOccupancy {
-  static constexpr int waves = GS_FWD_WAVES;
+  static constexpr int waves = (TB::S * F::D > 63) ? 1 : GS_FWD_WAVES;
 };
 
 
