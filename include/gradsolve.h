@@ -185,7 +185,9 @@ typedef struct gs_solve_args {
                             one lane per trajectory.  0 = none.  Needs the
                             queue schedule (else GS_ERR_UNSUPPORTED); the
                             tape (either mode) and output nodes are written
-                            record for record as one lane writes them.
+                            record for record as one lane writes them, and
+                            gs_solve_sens carries its tangents on the same
+                            groups (gs_solve_vjp has a `wide` of its own).
                             Explicit pairs only.  The groups
                             refill from their own queue; they and the single
                             lanes share the grid (the occupancy limit, or
