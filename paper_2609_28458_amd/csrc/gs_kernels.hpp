@@ -834,9 +834,11 @@ struct GroupTraj {
   int32_t ck_left;  // accepted steps until the next checkpoint
 };
 
-// One attempt of a group: the single-lane attempt() component by component.
-// on_accept(t_old, h, y_old) runs on acceptance with the new state in s and
-// the step's stages still in s.k, as in the single-lane attempt.
+// One attempt of a group: the single-lane attempt() component by component
+// (for a dual scalar type the error estimate and step control read the
+// values only, as one lane's do).  on_accept(t_old, h, y_old) runs on
+// acceptance with the new state in s and the step's stages still in s.k, as
+// in the single-lane attempt.
 template <class TB, class F, class T, class OnAccept>
 __device__ __forceinline__ Attempt group_attempt(const Params& P, const GroupCoef<TB>& cf,
                                                  GroupTraj<TB, F, T>& s, int c,
@@ -982,6 +984,10 @@ __device__ __forceinline__ T group_short_step(const typename F::template ParT<T>
 // exact hits directly, the others as deferred records (lane 0 the step's
 // start time and length, lane c component c of its start state), or with
 // INLOOP (a pair with a dense polynomial, no pending array) the dense value.
+// T = ad::Dual<M>: a sensitivity solve (no tape), lane c carrying component
+// c of the value and its M tangents; outputs are evaluated in the loop (the
+// dense value, or Verner 7's shortened step on the group) and the tangents
+// land in S_out and S_final as one lane writes them.
 template <class TB, class F, class T, bool NODES, bool TAPE, bool INLOOP>
 __device__ void solve_group(const Params& P, const SensParams& SP) {
   constexpr int D = F::D;
