@@ -121,3 +121,15 @@ def test_sensitivities_of_the_gradient_workload(orc):
     o = oracle_solve(orc, w, idx, sens_cols=[6, 7])
     np.testing.assert_array_equal(sol.n_accepted.cpu().numpy()[idx], o["n_accepted"])
     _close(S_final.cpu().numpy()[:, :, idx], o["S_final"], name="sens vs oracle, gradient workload sample")
+    # the launch the benchmark times: longest first, the longest 256 on
+    # 16-lane groups; bitwise the single-lane result, the 50 longest checked
+    # against the oracle as well
+    order = api.Solution(prob, api.Launch()).queue_order().clone()
+    g, G_final, _ = api.solve_sens(prob, [6, 7], api.Launch(wide=256), order=order)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(G_final.cpu().numpy(), S_final.cpu().numpy())
+    np.testing.assert_array_equal(g.y_final.cpu().numpy(), sol.y_final.cpu().numpy())
+    top = np.sort(np.argsort(-sol.n_accepted.cpu().numpy(), kind="stable")[:50])
+    o = oracle_solve(orc, w, top, sens_cols=[6, 7])
+    _close(G_final.cpu().numpy()[:, :, top], o["S_final"],
+           name="sens vs oracle, gradient workload, 50 longest on groups")
