@@ -99,13 +99,14 @@ def test_wide_group_sensitivities_equal_single_lanes(name, make, tab):
 def test_wide_group_sensitivities_of_stopped_trajectories(tab):
     """A step limit stops most trajectories: NaN outputs and tangents past
     the stop, statuses and counts, bitwise those of one lane each; a
-    longest-first order puts the longest on the groups."""
+    longest-first order puts the longest on the groups; outputs also in the
+    [K][n][d] layout."""
     w = {**inputs.orbits_forward(200, seed=55), "tableau": tab}
     prob = _prob(w)
     order = np.argsort(-inputs.predicted_cost(w), kind="stable")
-    for L in (dict(), dict(max_steps=120)):
+    for L in (dict(), dict(max_steps=120), dict(out_layout="knd")):
         r = _same_sens(prob, [6, 7], api.Launch(wide=64, **L), order=order)
-        if L:
+        if "max_steps" in L:
             assert np.any(r["status"] != 0)
 
 def test_sensitivities_of_the_gradient_workload(orc):
