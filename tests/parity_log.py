@@ -21,6 +21,7 @@ def allclose(name, got, ref, rtol, atol=0.0):
     lim = atol + rtol * np.abs(r)
     with np.errstate(divide="ignore", invalid="ignore"):
         q = np.where(lim > 0, np.abs(g - r) / lim, np.where(g == r, 0.0, np.inf))
+    q = np.where(np.isnan(g) & np.isnan(r), 0.0, q)
     worst = float(np.nanmax(q)) if q.size and not np.all(np.isnan(q)) else 0.0
     record(f"{name} (error / bar)", worst, 1.0)
     np.testing.assert_allclose(g, r, rtol=rtol, atol=atol, err_msg=name)
